@@ -1,0 +1,152 @@
+"""Synthetic workloads and seeded input generators for the VP-LBM time step.
+
+This module holds configuration only: grid sizes, boundary kinds, body parameters
+and seeded random states.  It contains none of the stream/collide/penalization
+arithmetic, imports nothing else from this package, and serves both the GPU path
+and the CPU oracle (through the tests and the benchmark).
+
+Parameter readings (the paper leaves these open; each reading is documented once in
+the design notes of the repository):
+
+* viscosity from the Reynolds number, nu = U0 D / Re, and the relaxation time from
+  nu = c_s^2 (tau - 1/2)  (Sec. 2.2, Eq. (6)); s_nu = 1/tau;
+* the remaining MRT rates (s_e, s_eps, s_q) = (1.64, 1.54, 1.9) with eta = 1e-3;
+* channel flows: west inlet by moving-wall half-way bounce-back at (U0, 0), east
+  convective outflow at U_c = U0, south/north free-slip symmetry (Sec. 3.1);
+* imposed oscillation y = y0 + A sin(2 pi f t) with A = 0.2 D and f = 0.2 U0 / D;
+* free VIV: mass = 10 x displaced fluid mass, stiffness from the reduced velocity
+  U_r = U0 / (f_n D), f_n = sqrt(k/m) / (2 pi), no damping;
+* sedimentation: closed box, density ratio 1.5, gravity from the confined-drag
+  settling law of Sec. 3.2 (Eqs. (33)-(35)) so that the particle Reynolds number is 1.
+"""
+import math
+
+import numpy as np
+
+RATES_BASE = (1.64, 1.54, 1.9)  # s_e, s_eps, s_q
+ETA = 1e-3
+
+
+def tau_from(U0: float, D: float, Re: float) -> float:
+    nu = U0 * D / Re
+    return 3.0 * nu + 0.5
+
+
+def rates_for_tau(tau: float, base=RATES_BASE):
+    return (base[0], base[1], base[2], 1.0 / tau)
+
+
+def channel_spec(nx, ny, U0, tau, eta=ETA, storage="fp32"):
+    return dict(nx=int(nx), ny=int(ny), rates=rates_for_tau(tau), eta=float(eta),
+                bc=("velocity", "outflow", "symmetry", "symmetry"),
+                u_wall=[[U0, 0.0], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
+                u_conv=float(U0), g_fluid=(0.0, 0.0), rho0=1.0, u0=(float(U0), 0.0),
+                storage=storage)
+
+
+def fixed_disc(D, x, y, smooth_delta=0.0):
+    return dict(radius=D / 2.0, x=float(x), y=float(y), theta=0.0, vx=0.0, vy=0.0, omega=0.0,
+                mode="fixed", free_mask=0, mass=1.0, inertia=1.0, k=(0.0,) * 3, c=(0.0,) * 3,
+                q0=(float(x), float(y), 0.0), f_ext=(0.0,) * 3, imp_amp=0.0, imp_freq=0.0,
+                imp_y0=float(y), smooth_delta=float(smooth_delta), internal_mass_correction=1)
+
+
+# ---- the five workloads -------------------------------------------------------------
+
+def imposed_oscillation(storage="fp64", nx=200, ny=80, D=20.0, U0=0.05, Re=100.0):
+    """200x80 channel, disc D=20 at (50, 40) in imposed transverse oscillation."""
+    tau = tau_from(U0, D, Re)
+    spec = channel_spec(nx, ny, U0, tau, storage=storage)
+    body = fixed_disc(D, nx / 4.0, ny / 2.0)
+    body.update(mode="imposed_sin", imp_amp=0.2 * D, imp_freq=0.2 * U0 / D, imp_y0=ny / 2.0)
+    return dict(name="imposed_oscillation_%dx%d" % (nx, ny), spec=spec, body=body, steps=2000,
+                U0=U0, D=D)
+
+
+def viv_body(D, x, y, U0, Ur, mass_ratio=10.0, damping=0.0):
+    m = mass_ratio * math.pi * D * D / 4.0  # mass ratio x displaced fluid mass (rho0 = 1)
+    fn = U0 / (Ur * D)
+    k = m * (2.0 * math.pi * fn) ** 2
+    b = fixed_disc(D, x, y)
+    b.update(mode="free", free_mask=0b010, mass=m, inertia=0.5 * m * (D / 2.0) ** 2,
+             k=(0.0, k, 0.0), c=(0.0, damping, 0.0), q0=(float(x), float(y), 0.0))
+    return b
+
+
+def free_viv(storage="fp32", nx=2048, ny=1024, D=40.0, U0=0.05, Re=150.0, Ur=5.0):
+    """2048x1024 channel, disc D=40 on a transverse spring (mass ratio 10, U_r = 5)."""
+    tau = tau_from(U0, D, Re)
+    spec = channel_spec(nx, ny, U0, tau, storage=storage)
+    body = viv_body(D, nx / 4.0, ny / 2.0, U0, Ur)
+    return dict(name="free_viv_%dx%d" % (nx, ny), spec=spec, body=body, steps=100000, U0=U0, D=D)
+
+
+def confinement_kappa(Ht: float) -> float:
+    """Wall-correction factor of the confined settling law (Sec. 3.2, Eq. (34))."""
+    return 1.0 / (math.log(Ht) - 0.9157 + 1.7244 * Ht ** -2 - 1.7302 * Ht ** -4
+                  + 2.4056 * Ht ** -6 - 4.5913 * Ht ** -8)
+
+
+def sedimentation(storage="fp32", nx=1024, ny=4096, D=32.0, x=512.0, y=3800.0, rho_ratio=1.5,
+                  tau=0.8, Re_p=1.0):
+    """Closed box, disc released from rest, free in x, y and theta under gravity."""
+    nu = (tau - 0.5) / 3.0
+    vs = Re_p * nu / D
+    kappa = confinement_kappa(nx / D)
+    g = 16.0 * kappa * nu * vs / (D * D * (rho_ratio - 1.0))  # mu = rho nu, rho = 1
+    R = D / 2.0
+    m = rho_ratio * math.pi * R * R
+    spec = dict(nx=int(nx), ny=int(ny), rates=rates_for_tau(tau), eta=ETA,
+                bc=("wall", "wall", "wall", "wall"), u_wall=[[0.0, 0.0]] * 4, u_conv=0.0,
+                g_fluid=(0.0, 0.0), rho0=1.0, u0=(0.0, 0.0), storage=storage)
+    body = fixed_disc(D, x, y)
+    body.update(mode="free", free_mask=0b111, mass=m, inertia=0.5 * m * R * R,
+                f_ext=(0.0, -m * (1.0 - 1.0 / rho_ratio) * g, 0.0))
+    return dict(name="sedimentation_%dx%d" % (nx, ny), spec=spec, body=body, steps=200000,
+                g=g, vs=vs, kappa=kappa, D=D, U0=vs)
+
+
+def batch_sweep(storage="fp32", n=64, seed=0, U0=0.05, Re=150.0):
+    """64 VIV runs of uneven size: ny ~ U{128..512}, nx = 2 ny, D = ny/12, U_r 2..12."""
+    rng = np.random.default_rng(seed)
+    nys = rng.integers(128, 513, n)
+    sims = []
+    for i, ny in enumerate(nys):
+        ny = int(ny)
+        nx = 2 * ny
+        D = ny / 12.0
+        Ur = 2.0 + 10.0 * i / max(n - 1, 1)
+        tau = tau_from(U0, D, Re)
+        spec = channel_spec(nx, ny, U0, tau, storage=storage)
+        body = viv_body(D, nx / 4.0, ny / 2.0, U0, Ur)
+        sims.append(dict(name="viv_%d_%dx%d" % (i, nx, ny), spec=spec, body=body, U0=U0, D=D))
+    return sims
+
+
+def adjoint_drag(storage="fp32", nx=1024, ny=512, D=32.0, U0=0.05, Re=100.0, delta=1.0):
+    """Fixed disc with a tanh-smoothed indicator (interface width 2 delta)."""
+    tau = tau_from(U0, D, Re)
+    spec = channel_spec(nx, ny, U0, tau, storage=storage)
+    body = fixed_disc(D, nx / 4.0, ny / 2.0, smooth_delta=delta)
+    return dict(name="adjoint_drag_%dx%d" % (nx, ny), spec=spec, body=body, steps=4000,
+                checkpoint_every=100, U0=U0, D=D)
+
+
+def roofline_grid(storage="fp32", n=8192, D=512.0, U0=0.05, Re=100.0):
+    tau = tau_from(U0, D, Re)
+    spec = channel_spec(n, n, U0, tau, storage=storage)
+    body = fixed_disc(D, n / 4.0, n / 2.0)
+    return dict(name="roofline_%dx%d" % (n, n), spec=spec, body=body, steps=200, U0=U0, D=D)
+
+
+# ---- seeded random states -------------------------------------------------------------
+
+LATTICE_WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def random_populations(nx, ny, seed=1234, amp=0.1):
+    """Post-collision populations w_a (1 + amp * xi), xi ~ U(-1, 1): a random,
+    positive, near-rest state used to drive the step-by-step comparisons."""
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=(9, ny, nx))
+    return LATTICE_WEIGHTS[:, None, None] * (1.0 + amp * xi)
