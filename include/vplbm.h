@@ -1,0 +1,201 @@
+/*
+ * vplbm.h -- C ABI of the MI355X (gfx950) volume-penalization lattice-Boltzmann
+ * library: one D2Q9 multiple-relaxation-time time step with the penalization force
+ * of a moving rigid disc, its force/torque and the rigid-body update.
+ *
+ * Method: Liberge & Beghein, "Fluid Structure Interaction modelling using Lattice
+ * Boltzmann and Volume Penalization method" (arXiv 1905.05110):
+ *   Sec. 2.1, Eqs. (1)-(2)      penalized Navier-Stokes, indicator chi of the solid;
+ *   Sec. 2.2, Eqs. (8)-(22)     MRT lattice Boltzmann with a Guo source, the implicit
+ *                               penalized velocity update (Eq. (22));
+ *   Sec. 2.3, Eqs. (23)-(24)    rigid-body translation/rotation, solved by RK4;
+ *   Algorithm 1                 order of one fluid-structure step.
+ * The force on the body is the volume integral of the penalization force,
+ * sum over nodes of rho chi/eta (u - u_s), instead of the momentum-exchange sum of
+ * Eqs. (25)-(27).
+ *
+ * Conventions for every call:
+ *   - Every function returns an int status (LBM_OK or a negative LBM_ERR_*); nothing
+ *     is thrown across the ABI.  lbm_last_error(sim) gives a message valid until the
+ *     next call on the same handle; lbm_last_error(NULL) gives the message of the last
+ *     failed lbm_create on this thread.
+ *   - Arguments are checked before any device call; a rejected call changes nothing.
+ *   - lbm_step only enqueues work on the simulation's HIP stream and returns launch
+ *     errors.  Errors during execution surface at the next synchronising call
+ *     (lbm_sync, lbm_forces, lbm_fields, lbm_get_populations, lbm_save).
+ *   - Host arrays are owned by the caller.  Device memory allocated by the library is
+ *     freed by lbm_destroy; device memory passed in through lbm_opts.pop_buffers is
+ *     owned by the caller and must outlive the simulation.
+ *   - A handle must not be used by two threads at once; separate handles are
+ *     independent.
+ *   - Fields and population arrays on the host are FP64, [ny][nx] (x fastest) or
+ *     [9][ny][nx], whatever the storage precision on the device.
+ *   - Lattice: node (i, j) sits at x = i, y = j (lattice units, dx = dt = 1); domain
+ *     walls sit half-way, at -1/2 and n - 1/2.  Directions: 0 rest, 1 E, 2 N, 3 W,
+ *     4 S, 5 NE, 6 NW, 7 SW, 8 SE (Sec. 2.2, Eq. (10)).
+ */
+#ifndef VPLBM_H
+#define VPLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_sim lbm_sim; /* opaque, owned by the library */
+
+enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,      /* invalid argument; nothing was done */
+    LBM_ERR_ALLOC = -2,    /* device or host allocation failed */
+    LBM_ERR_HIP = -3,      /* HIP runtime error (message in lbm_last_error) */
+    LBM_ERR_UNSTABLE = -4, /* a non-positive or non-finite density/velocity was met */
+    LBM_ERR_STATE = -5     /* call not valid in the current state */
+};
+
+/* Storage of the populations in device memory.  All forms store the offset
+ * g = f - w_a from the rest-state weights; arithmetic is FP64 for LBM_FP64 and FP32
+ * otherwise; force/torque reductions and the rigid body are always FP64.
+ * LBM_FP16_OFS stores round-to-nearest-even(g * 2^k) as IEEE binary16 (k =
+ * fp16_scale_log2); LBM_BF16_OFS stores round-to-nearest-even(g) as bfloat16. */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
+
+/* Boundary rule of one domain side (Sec. 3.1 for the channel set-up).
+ *   PERIODIC  wrap around (both opposite sides must be periodic);
+ *   WALL      no-slip half-way bounce-back;
+ *   VELOCITY  half-way bounce-back of a wall moving at u_wall (inlet of Sec. 3.1):
+ *             f_a = f~_opp(a) + 6 w_a (c_a . u_wall), wall density 1;
+ *   SYMMETRY  free-slip specular reflection (u . n = 0);
+ *   OUTFLOW   convective outflow df/dt + U_c df/dx = 0, implicit upwind in time
+ *             (east side only).
+ * At corners the west/east rule is applied first. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_VELOCITY = 2, LBM_BC_SYMMETRY = 3,
+       LBM_BC_OUTFLOW = 4 };
+enum { LBM_WEST = 0, LBM_EAST = 1, LBM_SOUTH = 2, LBM_NORTH = 3 };
+
+/* Body motion.  FIXED: pose constant (its velocities still enter u_s);
+ * IMPOSED_SIN: y = imp_y0 + imp_amp sin(2 pi imp_freq t), t = steps since
+ * lbm_set_body (shape of Sec. 3.1, Eq. (29)); FREE: Eqs. (23)-(24) by classical RK4
+ * with unit step and the fluid force frozen over the step, for the degrees of freedom
+ * set in free_mask (bit 0 x, bit 1 y, bit 2 theta), the others held; CONST_VEL: pose
+ * advances by its constant velocities every step. */
+enum { LBM_BODY_FIXED = 0, LBM_BODY_IMPOSED_SIN = 1, LBM_BODY_FREE = 2, LBM_BODY_CONST_VEL = 3 };
+
+/* MRT relaxation rates of the non-conserved moments (Sec. 2.2, Eq. (16)):
+ * s_e (energy), s_eps (energy square), s_q (heat fluxes), s_nu (stresses; 1/tau,
+ * nu = (tau - 1/2)/3 by Eq. (6)).  Each must lie in (0, 2).  The rates of the
+ * conserved moments do not change the result and are not inputs. */
+typedef struct {
+    double s_e, s_eps, s_q, s_nu;
+} lbm_rates;
+
+typedef struct {
+    int bc[4];             /* LBM_BC_* for west, east, south, north */
+    double u_wall[4][2];   /* wall velocity of each side (used by VELOCITY sides) */
+    double u_conv;         /* convective velocity U_c of an OUTFLOW side, >= 0 */
+    double g_fluid[2];     /* uniform body-force acceleration on the fluid */
+    double rho0, u0[2];    /* initial state f = f_eq(rho0, u0) everywhere */
+    int storage;           /* LBM_FP64 / LBM_FP32 / LBM_FP16_OFS / LBM_BF16_OFS */
+    int fp16_scale_log2;   /* k of the FP16 offset scale 2^k, 0..14 (default 10) */
+    int history_cap;       /* force records kept on the device between drains (default 65536) */
+    void* hip_stream;      /* hipStream_t to run on; NULL: the library creates one */
+    void* pop_buffers[2];  /* optional caller-owned device buffers of lbm_pop_bytes() each */
+} lbm_opts;
+
+typedef struct {
+    double radius, x, y, theta, vx, vy, omega; /* disc radius, pose and velocities at t = 0 */
+    int mode;                                  /* LBM_BODY_* */
+    unsigned free_mask;                        /* FREE: bit 0 x, bit 1 y, bit 2 theta */
+    double mass, inertia;                      /* m and I of Eqs. (23)-(24) */
+    double k[3], c[3], q0[3], f_ext[3];        /* stiffness, damping, rest pose, external load */
+    double imp_amp, imp_freq, imp_y0;          /* IMPOSED_SIN parameters */
+    double smooth_delta;                       /* 0: sharp chi (d^2 <= R^2); > 0: chi =
+                                                  1/(1 + exp(2 (d - R)/delta)), 0 beyond
+                                                  d - R > 20 delta, 1 below -20 delta */
+    int internal_mass_correction;              /* FREE bodies use F_vp + dP_in/dt if set */
+} lbm_body;
+
+/* Per-step record, written on the device for every step. */
+typedef struct {
+    int64_t step;      /* index of the step */
+    double fvp[2];     /* sum over nodes of rho chi/eta (u - u_s): force on the body */
+    double tvp;        /* its torque about the body centre */
+    double pin[3];     /* momentum and angular momentum of the fluid weighted by chi */
+    double fh[2], th;  /* force/torque driving a FREE body: fvp + (pin - pin_prev) when
+                          internal_mass_correction is set (zero on the first step) */
+    double q[3], v[3]; /* pose (x, y, theta) and velocities during this step */
+} lbm_force_rec;
+
+/* Fills o with defaults: periodic on all sides, rho0 = 1, u0 = 0, FP32 storage. */
+void lbm_default_opts(lbm_opts* o);
+
+/* Bytes of one population buffer (two are needed) for a grid and storage. */
+size_t lbm_pop_bytes(int nx, int ny, int storage);
+
+/* Creates a simulation on the current HIP device.  nx, ny >= 3; every rate in (0, 2);
+ * eta > 0 (penalization factor of Eq. (1)); opts NULL means lbm_default_opts.
+ * Periodic sides must come in opposite pairs; OUTFLOW only on the east side and then
+ * nx >= 3.  On success *out receives the handle. */
+int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts,
+               lbm_sim** out);
+
+/* Sets (or replaces) the rigid disc; allowed before and between steps.  radius > 0,
+ * mass > 0 and inertia > 0 for FREE bodies.  Resets the imposed-motion clock and the
+ * internal-momentum history. */
+int lbm_set_body(lbm_sim* sim, const lbm_body* body);
+
+/* Removes the body (chi = 0 everywhere). */
+int lbm_clear_body(lbm_sim* sim);
+
+/* Enqueues n >= 0 time steps (Algorithm 1) on the simulation's stream. */
+int lbm_step(lbm_sim* sim, int64_t n);
+
+/* Replays captured HIP graphs of k steps (k even, >= 2) inside lbm_step; k = 0 turns
+ * graphs off.  Results are identical with and without graphs. */
+int lbm_set_graph_steps(lbm_sim* sim, int k);
+
+/* Waits for the stream; LBM_ERR_UNSTABLE if an unstable state was met. */
+int lbm_sync(lbm_sim* sim);
+
+/* Synchronises, then copies the records of the steps not yet drained, oldest first,
+ * at most cap of them, into out; *n_out receives the count.  Records overwritten on
+ * the device before being drained (more than history_cap pending) are skipped. */
+int lbm_forces(lbm_sim* sim, lbm_force_rec* out, int64_t cap, int64_t* n_out);
+
+/* Synchronises, then writes density and penalized velocity (Eq. (22)) of the current
+ * state with the body at its current pose into host arrays of nx*ny doubles each. */
+int lbm_fields(lbm_sim* sim, double* rho, double* ux, double* uy);
+
+/* Debug access to the post-collision populations f (not offsets), host FP64
+ * [9][ny][nx]; set is rounded to the storage precision. */
+int lbm_set_populations(lbm_sim* sim, const double* f);
+int lbm_get_populations(lbm_sim* sim, double* f);
+
+/* Synchronises and returns the body pose and velocities (3 doubles each). */
+int lbm_get_body_state(lbm_sim* sim, double* q, double* v);
+
+/* Number of steps enqueued since creation. */
+int64_t lbm_step_index(const lbm_sim* sim);
+
+/* Enqueues n steps with a HIP event pair around every kernel launch, synchronises and
+ * returns the summed kernel time (ms) and the wall time of the whole region (ms). */
+int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms);
+
+/* Serialises the full state (populations, outflow memory, body, step index) into a
+ * host buffer; with buf NULL only *size_out is set.  lbm_load restores a state saved
+ * from a simulation of the same grid and storage. */
+int lbm_save(lbm_sim* sim, void* buf, size_t cap, size_t* size_out);
+int lbm_load(lbm_sim* sim, const void* buf, size_t size);
+
+/* Frees everything the library allocated for the simulation. */
+int lbm_destroy(lbm_sim* sim);
+
+const char* lbm_last_error(const lbm_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPLBM_H */

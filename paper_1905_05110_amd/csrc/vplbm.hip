@@ -1,0 +1,748 @@
+// vplbm.hip -- kernels and host runtime behind the C ABI of include/vplbm.h.
+//
+// One lbm_step launch = one fluid-structure step of Algorithm 1 (Liberge & Beghein,
+// arXiv 1905.05110): every workgroup pulls, penalizes, collides and stores one row
+// segment; the workgroups that meet the body reduce its force/torque in FP64 and the
+// last of them advances the body on the device, so consecutive steps need no host
+// round trip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vplbm.h"
+#include "vplbm_device.hpp"
+
+using namespace vplbm;
+
+// ---------------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ dp, int p) {
+    const SimDesc& d = *dp;
+    step_tile<S>(d, xcd_tile((int)blockIdx.x, (int)gridDim.x), p);
+}
+
+// Fill both buffers' planes with constant offsets (initial equilibrium).
+template <class S>
+__global__ void k_fill(SimDesc d, double g0, double g1, double g2, double g3, double g4, double g5,
+                       double g6, double g7, double g8, int buf) {
+    using T = typename Codec<S>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const double g[NQ] = {g0, g1, g2, g3, g4, g5, g6, g7, g8};
+    S* f = reinterpret_cast<S*>(d.pop[buf]);
+    const long long base = (long long)j * d.pitch + i;
+    for (int a = 0; a < NQ; ++a) Codec<S>::store(f, a * d.ps + base, (T)g[a], d.scale);
+}
+
+// Host FP64 populations f [9][ny][nx] <-> stored offsets.
+template <class S>
+__global__ void k_set_pop(SimDesc d, const double* __restrict__ f, int buf) {
+    using T = typename Codec<S>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    S* dst = reinterpret_cast<S*>(d.pop[buf]);
+    const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const long long base = (long long)j * d.pitch + i;
+    const long long plane = (long long)d.nx * d.ny;
+    for (int a = 0; a < NQ; ++a) {
+        const double v = f[a * plane + (long long)j * d.nx + i] - w[a];
+        Codec<S>::store(dst, a * d.ps + base, (T)v, d.scale);
+    }
+}
+
+template <class S>
+__global__ void k_get_pop(SimDesc d, double* __restrict__ f, int buf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const S* src = reinterpret_cast<const S*>(d.pop[buf]);
+    const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const long long base = (long long)j * d.pitch + i;
+    const long long plane = (long long)d.nx * d.ny;
+    for (int a = 0; a < NQ; ++a)
+        f[a * plane + (long long)j * d.nx + i] =
+            (double)Codec<S>::load(src, a * d.ps + base, d.inv_scale) + w[a];
+}
+
+// Density and penalized velocity of the current state, body at its current pose.
+template <class S>
+__global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
+    using T = typename Codec<S>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const S* fin = reinterpret_cast<const S*>(d.pop[p]);
+    T g[NQ];
+    pull_node<S>(d, fin, i, j, g, false);
+    const BodyDev& B = *d.body;
+    double chi = 0.0, usx = 0.0, usy = 0.0;
+    if (B.active) {
+        const double rx = (double)i - B.q[p][0], ry = (double)j - B.q[p][1];
+        chi = disc_chi(B, disc_d2(rx, ry));
+        usx = B.v[p][0] - B.v[p][2] * ry;
+        usy = B.v[p][1] + B.v[p][2] * rx;
+    }
+    T drho, jx, jy, Gx, Gy;
+    NodeOut<T> o;
+    macros<T>(d, g, (T)chi, (T)usx, (T)usy, drho, jx, jy, o, Gx, Gy);
+    const long long plane = (long long)d.nx * d.ny, o_ = (long long)j * d.nx + i;
+    out[o_] = (double)o.rho;
+    out[plane + o_] = (double)o.ux;
+    out[2 * plane + o_] = (double)o.uy;
+}
+
+// ---------------------------------------------------------------------------------
+// host runtime
+// ---------------------------------------------------------------------------------
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t elem_size(int storage) {
+    switch (storage) {
+        case LBM_FP64: return 8;
+        case LBM_FP32: return 4;
+        default: return 2;
+    }
+}
+
+int row_pitch(int nx) { return (nx + 63) / 64 * 64; }
+
+long long plane_stride(int nx, int ny) {
+    // pad planes by 5 x 64 elements so the nine streams do not start on the same
+    // large power-of-two boundary
+    return (long long)row_pitch(nx) * ny + 320;
+}
+
+}  // namespace
+
+struct lbm_sim {
+    int nx = 0, ny = 0, storage = LBM_FP32;
+    size_t pop_bytes = 0;
+    void* pop[2] = {nullptr, nullptr};
+    bool own_pop = false;
+    void* outlet = nullptr;
+    BodyDev* body_d = nullptr;
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    Record* hist = nullptr;
+    int* flag = nullptr;
+    double* staging = nullptr;  // FP64 [9][ny][nx] for set/get/fields
+    SimDesc desc{};
+    SimDesc* desc_d = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t host_step = 0;
+    int64_t drained = 0;
+    int hist_cap = 65536;
+    lbm_opts opts{};
+    lbm_rates rates{};
+    double eta = 0.0;
+    BodyDev body_h{};
+    std::string err;
+    int graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+#define HIP_TRY(sim, expr)                                                             \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (sim)->err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+            return LBM_ERR_HIP;                                                        \
+        }                                                                              \
+    } while (0)
+
+static int fail(lbm_sim* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+static dim3 grid_rows(const lbm_sim* s) { return dim3((s->nx + 255) / 256, s->ny); }
+
+template <class F>
+static int dispatch(int storage, F&& f) {
+    switch (storage) {
+        case LBM_FP64: return f((double*)nullptr);
+        case LBM_FP32: return f((float*)nullptr);
+        case LBM_FP16_OFS: return f((_Float16*)nullptr);
+        default: return f((bf16s*)nullptr);
+    }
+}
+
+// Offsets of the equilibrium f_eq(rho, u) - w (Eq. (11)), evaluated in FP64.
+static void eq_offsets(double rho, double ux, double uy, double g[NQ]) {
+    static const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double usq = ux * ux + uy * uy;
+    for (int a = 0; a < NQ; ++a) {
+        const double cu = dir_cx(a) * ux + dir_cy(a) * uy;
+        g[a] = w[a] * (rho - 1.0) + w[a] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    }
+}
+
+static int upload_desc(lbm_sim* s) {
+    HIP_TRY(s, hipMemcpyAsync(s->desc_d, &s->desc, sizeof(SimDesc), hipMemcpyHostToDevice,
+                              s->stream));
+    return LBM_OK;
+}
+
+static void drop_graph(lbm_sim* s) {
+    if (s->gexec) hipGraphExecDestroy(s->gexec);
+    if (s->graph) hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+}
+
+static int launch_step(lbm_sim* s) {
+    const int p = (int)(s->host_step & 1);
+    const int ntiles = s->desc.tiles_x * s->desc.tiles_y;
+    int rc = dispatch(s->storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_step<S>, dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p);
+        return LBM_OK;
+    });
+    if (rc) return rc;
+    HIP_TRY(s, hipGetLastError());
+    s->host_step += 1;
+    return LBM_OK;
+}
+
+extern "C" {
+
+void lbm_default_opts(lbm_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    for (int k = 0; k < 4; ++k) o->bc[k] = LBM_BC_PERIODIC;
+    o->rho0 = 1.0;
+    o->storage = LBM_FP32;
+    o->fp16_scale_log2 = 10;
+    o->history_cap = 65536;
+}
+
+size_t lbm_pop_bytes(int nx, int ny, int storage) {
+    if (nx < 1 || ny < 1 || storage < LBM_FP64 || storage > LBM_BF16_OFS) return 0;
+    return (size_t)NQ * (size_t)plane_stride(nx, ny) * elem_size(storage);
+}
+
+const char* lbm_last_error(const lbm_sim* sim) {
+    return sim ? sim->err.c_str() : g_create_error.c_str();
+}
+
+static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o, std::string& m) {
+    if (nx < 3 || ny < 3) return m = "nx and ny must be >= 3", LBM_ERR_ARG;
+    if ((long long)nx * ny > (1LL << 31)) return m = "grid too large", LBM_ERR_ARG;
+    const double rr[4] = {r.s_e, r.s_eps, r.s_q, r.s_nu};
+    for (double x : rr)
+        if (!(x > 0.0 && x < 2.0)) return m = "relaxation rates must lie in (0, 2)", LBM_ERR_ARG;
+    if (!(eta > 0.0) || !std::isfinite(eta)) return m = "eta must be > 0", LBM_ERR_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (o.bc[k] < LBM_BC_PERIODIC || o.bc[k] > LBM_BC_OUTFLOW)
+            return m = "unknown boundary kind", LBM_ERR_ARG;
+    if ((o.bc[0] == LBM_BC_PERIODIC) != (o.bc[1] == LBM_BC_PERIODIC) ||
+        (o.bc[2] == LBM_BC_PERIODIC) != (o.bc[3] == LBM_BC_PERIODIC))
+        return m = "periodic sides must come in opposite pairs", LBM_ERR_ARG;
+    if (o.bc[0] == LBM_BC_OUTFLOW || o.bc[2] == LBM_BC_OUTFLOW || o.bc[3] == LBM_BC_OUTFLOW)
+        return m = "OUTFLOW is only supported on the east side", LBM_ERR_ARG;
+    if (!(o.u_conv >= 0.0)) return m = "u_conv must be >= 0", LBM_ERR_ARG;
+    if (o.storage < LBM_FP64 || o.storage > LBM_BF16_OFS) return m = "unknown storage", LBM_ERR_ARG;
+    if (o.storage == LBM_FP16_OFS && (o.fp16_scale_log2 < 0 || o.fp16_scale_log2 > 14))
+        return m = "fp16_scale_log2 must lie in 0..14", LBM_ERR_ARG;
+    if (o.history_cap < 1) return m = "history_cap must be >= 1", LBM_ERR_ARG;
+    if (!(o.rho0 > 0.0)) return m = "rho0 must be > 0", LBM_ERR_ARG;
+    if ((o.pop_buffers[0] == nullptr) != (o.pop_buffers[1] == nullptr))
+        return m = "pass both population buffers or neither", LBM_ERR_ARG;
+    return LBM_OK;
+}
+
+static void free_sim(lbm_sim* s) {
+    drop_graph(s);
+    if (s->own_pop) {
+        if (s->pop[0]) hipFree(s->pop[0]);
+        if (s->pop[1]) hipFree(s->pop[1]);
+    }
+    void* bufs[] = {s->outlet, s->body_d, s->partials, s->counter, s->hist, s->flag, s->staging,
+                    s->desc_d};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts, lbm_sim** out) {
+    if (!out) return g_create_error = "out is NULL", LBM_ERR_ARG;
+    *out = nullptr;
+    lbm_opts o;
+    if (opts)
+        o = *opts;
+    else
+        lbm_default_opts(&o);
+    if (o.history_cap == 0) o.history_cap = 65536;
+    std::string msg;
+    int rc = check_opts(nx, ny, rates, eta, o, msg);
+    if (rc) return g_create_error = msg, rc;
+
+    lbm_sim* s = new lbm_sim();
+    s->nx = nx;
+    s->ny = ny;
+    s->storage = o.storage;
+    s->opts = o;
+    s->rates = rates;
+    s->eta = eta;
+    s->hist_cap = o.history_cap;
+    s->pop_bytes = lbm_pop_bytes(nx, ny, o.storage);
+    auto bail = [&](int code) {
+        g_create_error = s->err;
+        free_sim(s);
+        return code;
+    };
+#define CREATE_TRY(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            s->err = std::string(#expr) + ": " + hipGetErrorString(e_);                    \
+            return bail(e_ == hipErrorOutOfMemory ? LBM_ERR_ALLOC : LBM_ERR_HIP);          \
+        }                                                                                  \
+    } while (0)
+    int ndev = 0;
+    CREATE_TRY(hipGetDeviceCount(&ndev));
+    if (ndev < 1) return s->err = "no HIP device", bail(LBM_ERR_HIP);
+    if (o.hip_stream) {
+        s->stream = (hipStream_t)o.hip_stream;
+    } else {
+        CREATE_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        s->own_stream = true;
+    }
+    if (o.pop_buffers[0]) {
+        s->pop[0] = o.pop_buffers[0];
+        s->pop[1] = o.pop_buffers[1];
+    } else {
+        s->own_pop = true;
+        CREATE_TRY(hipMalloc(&s->pop[0], s->pop_bytes));
+        CREATE_TRY(hipMalloc(&s->pop[1], s->pop_bytes));
+    }
+    const size_t tsz = o.storage == LBM_FP64 ? 8 : 4;
+    const int tiles_x = (nx + TILE_X - 1) / TILE_X;
+    const int ntiles = tiles_x * ny;
+    CREATE_TRY(hipMalloc(&s->outlet, 3 * (size_t)ny * tsz));
+    CREATE_TRY(hipMalloc((void**)&s->body_d, sizeof(BodyDev)));
+    CREATE_TRY(hipMalloc((void**)&s->partials, (size_t)ntiles * 6 * sizeof(double)));
+    CREATE_TRY(hipMalloc((void**)&s->counter, 64));
+    CREATE_TRY(hipMalloc((void**)&s->hist, (size_t)s->hist_cap * sizeof(Record)));
+    CREATE_TRY(hipMalloc((void**)&s->flag, 64));
+    CREATE_TRY(hipMalloc((void**)&s->staging, (size_t)NQ * nx * ny * sizeof(double)));
+    CREATE_TRY(hipMalloc((void**)&s->desc_d, sizeof(SimDesc)));
+
+    SimDesc& d = s->desc;
+    d.pop[0] = s->pop[0];
+    d.pop[1] = s->pop[1];
+    d.outlet = s->outlet;
+    d.body = s->body_d;
+    d.partials = s->partials;
+    d.counter = s->counter;
+    d.hist = s->hist;
+    d.flag = s->flag;
+    d.ps = plane_stride(nx, ny);
+    d.nx = nx;
+    d.ny = ny;
+    d.pitch = row_pitch(nx);
+    d.tiles_x = tiles_x;
+    d.tiles_y = ny;
+    d.hist_cap = s->hist_cap;
+    for (int k = 0; k < 4; ++k) d.bc[k] = o.bc[k];
+    d.s_e = rates.s_e;
+    d.s_eps = rates.s_eps;
+    d.s_q = rates.s_q;
+    d.s_nu = rates.s_nu;
+    d.inv_eta = 1.0 / eta;
+    d.gx = o.g_fluid[0];
+    d.gy = o.g_fluid[1];
+    d.u_conv = o.u_conv;
+    static const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int side = 0; side < 4; ++side)
+        for (int a = 0; a < NQ; ++a)
+            d.bbc[side][a] =
+                6.0 * w[a] * (dir_cx(a) * o.u_wall[side][0] + dir_cy(a) * o.u_wall[side][1]);
+    if (o.storage == LBM_FP16_OFS) {
+        d.scale = std::ldexp(1.0f, o.fp16_scale_log2);
+        d.inv_scale = std::ldexp(1.0f, -o.fp16_scale_log2);
+    } else {
+        d.scale = 1.0f;
+        d.inv_scale = 1.0f;
+    }
+
+    // initial state: equilibrium at (rho0, u0) in both buffers, outflow memory alike
+    CREATE_TRY(hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream));
+    CREATE_TRY(hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream));
+    CREATE_TRY(hipMemsetAsync(s->counter, 0, 64, s->stream));
+    CREATE_TRY(hipMemsetAsync(s->flag, 0, 64, s->stream));
+    double g[NQ];
+    eq_offsets(o.rho0, o.u0[0], o.u0[1], g);
+    dispatch(o.storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        for (int b = 0; b < 2; ++b)
+            hipLaunchKernelGGL(k_fill<S>, grid_rows(s), dim3(256), 0, s->stream, d, g[0], g[1],
+                               g[2], g[3], g[4], g[5], g[6], g[7], g[8], b);
+        return 0;
+    });
+    CREATE_TRY(hipGetLastError());
+    {
+        std::vector<double> o64(3 * (size_t)ny);
+        std::vector<float> o32(3 * (size_t)ny);
+        const int dirs[3] = {3, 6, 7};
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < ny; ++j) {
+                o64[(size_t)k * ny + j] = g[dirs[k]];
+                o32[(size_t)k * ny + j] = (float)g[dirs[k]];
+            }
+        if (tsz == 8)
+            CREATE_TRY(hipMemcpy(s->outlet, o64.data(), o64.size() * 8, hipMemcpyHostToDevice));
+        else
+            CREATE_TRY(hipMemcpy(s->outlet, o32.data(), o32.size() * 4, hipMemcpyHostToDevice));
+    }
+    std::memset(&s->body_h, 0, sizeof(BodyDev));
+    s->body_h.active = 0;
+    s->body_h.step = 0;
+    CREATE_TRY(hipMemcpyAsync(s->body_d, &s->body_h, sizeof(BodyDev), hipMemcpyHostToDevice,
+                              s->stream));
+    CREATE_TRY(hipMemcpyAsync(s->desc_d, &s->desc, sizeof(SimDesc), hipMemcpyHostToDevice,
+                              s->stream));
+    CREATE_TRY(hipStreamSynchronize(s->stream));
+#undef CREATE_TRY
+    *out = s;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_sim* s) {
+    if (!s) return LBM_ERR_ARG;
+    hipStreamSynchronize(s->stream);
+    free_sim(s);
+    return LBM_OK;
+}
+
+static int sync_check(lbm_sim* s) {
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    int flag = 0;
+    HIP_TRY(s, hipMemcpy(&flag, s->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) return fail(s, LBM_ERR_UNSTABLE, "non-positive or non-finite density/velocity met");
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_sim* s) {
+    if (!s) return LBM_ERR_ARG;
+    return sync_check(s);
+}
+
+int lbm_set_body(lbm_sim* s, const lbm_body* b) {
+    if (!s || !b) return fail(s, LBM_ERR_ARG, "NULL argument");
+    if (!(b->radius > 0.0) || !std::isfinite(b->radius))
+        return fail(s, LBM_ERR_ARG, "radius must be > 0");
+    if (b->mode < LBM_BODY_FIXED || b->mode > LBM_BODY_CONST_VEL)
+        return fail(s, LBM_ERR_ARG, "unknown body mode");
+    if (b->mode == LBM_BODY_FREE && (!(b->mass > 0.0) || !(b->inertia > 0.0)))
+        return fail(s, LBM_ERR_ARG, "FREE bodies need mass > 0 and inertia > 0");
+    if (!(b->smooth_delta >= 0.0)) return fail(s, LBM_ERR_ARG, "smooth_delta must be >= 0");
+    if (b->free_mask > 7u) return fail(s, LBM_ERR_ARG, "free_mask has bits beyond x, y, theta");
+    const double vals[] = {b->x, b->y, b->theta, b->vx, b->vy, b->omega};
+    for (double x : vals)
+        if (!std::isfinite(x)) return fail(s, LBM_ERR_ARG, "non-finite pose or velocity");
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    BodyDev B;
+    std::memset(&B, 0, sizeof(B));
+    B.active = 1;
+    B.mode = b->mode;
+    B.free_mask = b->free_mask;
+    B.imc = b->internal_mass_correction ? 1 : 0;
+    B.smooth = b->smooth_delta > 0.0;
+    B.R = b->radius;
+    B.R2 = b->radius * b->radius;
+    B.delta = b->smooth_delta;
+    B.reach = B.smooth ? b->radius + 20.0 * b->smooth_delta : b->radius;
+    B.mass = b->mass;
+    B.inertia = b->inertia;
+    for (int k = 0; k < 3; ++k) {
+        B.k[k] = b->k[k];
+        B.c[k] = b->c[k];
+        B.q0[k] = b->q0[k];
+        B.fext[k] = b->f_ext[k];
+    }
+    B.amp = b->imp_amp;
+    B.freq = b->imp_freq;
+    B.y0 = b->imp_y0;
+    const int p = (int)(s->host_step & 1);
+    double q[3] = {b->x, b->y, b->theta}, v[3] = {b->vx, b->vy, b->omega};
+    if (b->mode == LBM_BODY_IMPOSED_SIN) {
+        q[1] = b->imp_y0;  // sin(0) = 0
+        v[1] = 6.283185307179586476925286766559 * b->imp_freq * b->imp_amp;
+    }
+    for (int k = 0; k < 3; ++k) {
+        B.q[p][k] = B.q[p ^ 1][k] = q[k];
+        B.v[p][k] = B.v[p ^ 1][k] = v[k];
+    }
+    B.t_body = 0;
+    B.step = s->host_step;
+    B.pin_valid = 0;
+    s->body_h = B;
+    HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_clear_body(lbm_sim* s) {
+    if (!s) return LBM_ERR_ARG;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    BodyDev B;
+    HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
+    B.active = 0;
+    B.pin_valid = 0;
+    HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_sim* s, int k) {
+    if (!s) return LBM_ERR_ARG;
+    if (k != 0 && (k < 2 || (k & 1))) return fail(s, LBM_ERR_ARG, "graph steps must be 0 or even >= 2");
+    drop_graph(s);
+    s->graph_steps = k;
+    return LBM_OK;
+}
+
+static int capture_graph(lbm_sim* s) {
+    // the graph holds graph_steps launches with parities 0, 1, 0, 1, ...
+    const int64_t saved = s->host_step;
+    s->host_step = 0;
+    HIP_TRY(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_OK;
+    for (int k = 0; k < s->graph_steps && rc == LBM_OK; ++k) rc = launch_step(s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    s->host_step = saved;
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(s, LBM_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+    s->graph = g;
+    HIP_TRY(s, hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+int lbm_step(lbm_sim* s, int64_t n) {
+    if (!s) return LBM_ERR_ARG;
+    if (n < 0) return fail(s, LBM_ERR_ARG, "n must be >= 0");
+    int64_t done = 0;
+    if (s->graph_steps > 0 && n >= s->graph_steps) {
+        if ((s->host_step & 1) && done < n) {
+            int rc = launch_step(s);
+            if (rc) return rc;
+            ++done;
+        }
+        if (!s->gexec) {
+            int rc = capture_graph(s);
+            if (rc) return rc;
+        }
+        while (n - done >= s->graph_steps) {
+            HIP_TRY(s, hipGraphLaunch(s->gexec, s->stream));
+            s->host_step += s->graph_steps;
+            done += s->graph_steps;
+        }
+    }
+    for (; done < n; ++done) {
+        int rc = launch_step(s);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_step_timed(lbm_sim* s, int64_t n, double* kernel_ms, double* region_ms) {
+    if (!s || n < 0) return fail(s, LBM_ERR_ARG, "bad argument");
+    std::vector<hipEvent_t> ev(2 * (size_t)n + 2);
+    for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
+    HIP_TRY(s, hipEventRecord(ev[0], s->stream));
+    int rc = LBM_OK;
+    for (int64_t k = 0; k < n && rc == LBM_OK; ++k) {
+        hipEventRecord(ev[2 + 2 * k], s->stream);
+        rc = launch_step(s);
+        hipEventRecord(ev[3 + 2 * k], s->stream);
+    }
+    HIP_TRY(s, hipEventRecord(ev[1], s->stream));
+    HIP_TRY(s, hipEventSynchronize(ev[1]));
+    double ksum = 0.0;
+    float ms = 0.f;
+    for (int64_t k = 0; k < n; ++k) {
+        hipEventElapsedTime(&ms, ev[2 + 2 * k], ev[3 + 2 * k]);
+        ksum += ms;
+    }
+    hipEventElapsedTime(&ms, ev[0], ev[1]);
+    for (auto& e : ev) hipEventDestroy(e);
+    if (rc) return rc;
+    if (kernel_ms) *kernel_ms = ksum;
+    if (region_ms) *region_ms = ms;
+    return LBM_OK;
+}
+
+int64_t lbm_step_index(const lbm_sim* s) { return s ? s->host_step : -1; }
+
+int lbm_forces(lbm_sim* s, lbm_force_rec* out, int64_t cap, int64_t* n_out) {
+    if (!s || (!out && cap > 0) || cap < 0) return fail(s, LBM_ERR_ARG, "bad argument");
+    int rc = sync_check(s);
+    if (n_out) *n_out = 0;
+    BodyDev B;
+    HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
+    const int64_t written = B.step;  // records exist for steps < B.step
+    if (s->drained < written - s->hist_cap) s->drained = written - s->hist_cap;
+    int64_t n = std::min<int64_t>(written - s->drained, cap);
+    static_assert(sizeof(Record) == sizeof(lbm_force_rec), "record layout");
+    for (int64_t k = 0; k < n;) {
+        const int64_t st = s->drained + k;
+        const int64_t slot = st % s->hist_cap;
+        const int64_t run = std::min<int64_t>(n - k, s->hist_cap - slot);
+        HIP_TRY(s, hipMemcpy(out + k, s->hist + slot, run * sizeof(Record), hipMemcpyDeviceToHost));
+        k += run;
+    }
+    s->drained += n;
+    if (n_out) *n_out = n;
+    return rc;
+}
+
+int lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy) {
+    if (!s || !rho || !ux || !uy) return fail(s, LBM_ERR_ARG, "NULL argument");
+    const int p = (int)(s->host_step & 1);
+    dispatch(s->storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_fields<S>, grid_rows(s), dim3(256), 0, s->stream, s->desc,
+                           s->staging, p);
+        return 0;
+    });
+    HIP_TRY(s, hipGetLastError());
+    int rc = sync_check(s);
+    const size_t plane = (size_t)s->nx * s->ny;
+    HIP_TRY(s, hipMemcpy(rho, s->staging, plane * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(s, hipMemcpy(ux, s->staging + plane, plane * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(s, hipMemcpy(uy, s->staging + 2 * plane, plane * 8, hipMemcpyDeviceToHost));
+    return rc;
+}
+
+int lbm_set_populations(lbm_sim* s, const double* f) {
+    if (!s || !f) return fail(s, LBM_ERR_ARG, "NULL argument");
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const size_t n = (size_t)NQ * s->nx * s->ny;
+    HIP_TRY(s, hipMemcpy(s->staging, f, n * 8, hipMemcpyHostToDevice));
+    const int p = (int)(s->host_step & 1);
+    dispatch(s->storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_set_pop<S>, grid_rows(s), dim3(256), 0, s->stream, s->desc,
+                           s->staging, p);
+        return 0;
+    });
+    HIP_TRY(s, hipGetLastError());
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_sim* s, double* f) {
+    if (!s || !f) return fail(s, LBM_ERR_ARG, "NULL argument");
+    const int p = (int)(s->host_step & 1);
+    dispatch(s->storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        hipLaunchKernelGGL(k_get_pop<S>, grid_rows(s), dim3(256), 0, s->stream, s->desc,
+                           s->staging, p);
+        return 0;
+    });
+    HIP_TRY(s, hipGetLastError());
+    int rc = sync_check(s);
+    HIP_TRY(s, hipMemcpy(f, s->staging, (size_t)NQ * s->nx * s->ny * 8, hipMemcpyDeviceToHost));
+    return rc;
+}
+
+int lbm_get_body_state(lbm_sim* s, double* q, double* v) {
+    if (!s || !q || !v) return fail(s, LBM_ERR_ARG, "NULL argument");
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    BodyDev B;
+    HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
+    const int p = (int)(s->host_step & 1);
+    for (int k = 0; k < 3; ++k) {
+        q[k] = B.q[p][k];
+        v[k] = B.v[p][k];
+    }
+    return LBM_OK;
+}
+
+// ---- save / load -------------------------------------------------------------------
+struct SaveHeader {
+    char magic[8];
+    int version, nx, ny, storage;
+    long long host_step, drained;
+    unsigned long long pop_bytes, outlet_bytes;
+};
+
+int lbm_save(lbm_sim* s, void* buf, size_t cap, size_t* size_out) {
+    if (!s || !size_out) return fail(s, LBM_ERR_ARG, "NULL argument");
+    const size_t tsz = s->storage == LBM_FP64 ? 8 : 4;
+    const size_t ob = 3 * (size_t)s->ny * tsz;
+    const size_t total = sizeof(SaveHeader) + s->pop_bytes + ob + sizeof(BodyDev);
+    *size_out = total;
+    if (!buf) return LBM_OK;
+    if (cap < total) return fail(s, LBM_ERR_ARG, "buffer too small");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    SaveHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "VPLBMS1", 8);
+    h.version = 1;
+    h.nx = s->nx;
+    h.ny = s->ny;
+    h.storage = s->storage;
+    h.host_step = s->host_step;
+    h.drained = s->drained;
+    h.pop_bytes = s->pop_bytes;
+    h.outlet_bytes = ob;
+    char* c = (char*)buf;
+    std::memcpy(c, &h, sizeof(h));
+    c += sizeof(h);
+    HIP_TRY(s, hipMemcpy(c, s->pop[s->host_step & 1], s->pop_bytes, hipMemcpyDeviceToHost));
+    c += s->pop_bytes;
+    HIP_TRY(s, hipMemcpy(c, s->outlet, ob, hipMemcpyDeviceToHost));
+    c += ob;
+    HIP_TRY(s, hipMemcpy(c, s->body_d, sizeof(BodyDev), hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+int lbm_load(lbm_sim* s, const void* buf, size_t size) {
+    if (!s || !buf) return fail(s, LBM_ERR_ARG, "NULL argument");
+    if (size < sizeof(SaveHeader)) return fail(s, LBM_ERR_ARG, "buffer too small");
+    SaveHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    const size_t tsz = s->storage == LBM_FP64 ? 8 : 4;
+    const size_t ob = 3 * (size_t)s->ny * tsz;
+    if (std::memcmp(h.magic, "VPLBMS1", 8) != 0 || h.version != 1 || h.nx != s->nx ||
+        h.ny != s->ny || h.storage != s->storage || h.pop_bytes != s->pop_bytes ||
+        h.outlet_bytes != ob || size < sizeof(h) + s->pop_bytes + ob + sizeof(BodyDev))
+        return fail(s, LBM_ERR_ARG, "saved state does not match this simulation");
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const char* c = (const char*)buf + sizeof(h);
+    s->host_step = h.host_step;
+    s->drained = h.drained;
+    HIP_TRY(s, hipMemcpy(s->pop[s->host_step & 1], c, s->pop_bytes, hipMemcpyHostToDevice));
+    c += s->pop_bytes;
+    HIP_TRY(s, hipMemcpy(s->outlet, c, ob, hipMemcpyHostToDevice));
+    c += ob;
+    HIP_TRY(s, hipMemcpy(s->body_d, c, sizeof(BodyDev), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemset(s->flag, 0, sizeof(int)));
+    drop_graph(s);
+    return LBM_OK;
+}
+
+}  // extern "C"

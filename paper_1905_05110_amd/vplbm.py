@@ -1,0 +1,276 @@
+"""Python binding of the HIP library ``libvplbm.so`` (C ABI of ``include/vplbm.h``).
+
+Argument marshalling only: every step of the method runs in the library's kernels.
+PyTorch, when given, supplies the device memory of the two population buffers and
+the HIP stream; there is no CPU fallback -- a missing library raises at import of
+the first simulation.
+
+A simulation is described by two dicts (``spec`` and ``body``, see ``workloads``).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvplbm.so")
+
+LBM_OK, LBM_ERR_ARG, LBM_ERR_ALLOC, LBM_ERR_HIP, LBM_ERR_UNSTABLE, LBM_ERR_STATE = 0, -1, -2, -3, -4, -5
+STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+BC = {"periodic": 0, "wall": 1, "velocity": 2, "symmetry": 3, "outflow": 4}
+MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
+
+EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
+           "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
+           "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
+           "lbm_step_index", "lbm_step_timed", "lbm_save", "lbm_load", "lbm_destroy",
+           "lbm_last_error"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("vplbm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Rates(C.Structure):
+    _fields_ = [("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
+                ("s_nu", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("bc", C.c_int * 4), ("u_wall", (C.c_double * 2) * 4), ("u_conv", C.c_double),
+                ("g_fluid", C.c_double * 2), ("rho0", C.c_double), ("u0", C.c_double * 2),
+                ("storage", C.c_int), ("fp16_scale_log2", C.c_int), ("history_cap", C.c_int),
+                ("hip_stream", C.c_void_p), ("pop_buffers", C.c_void_p * 2)]
+
+
+class Body(C.Structure):
+    _fields_ = [("radius", C.c_double), ("x", C.c_double), ("y", C.c_double),
+                ("theta", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
+                ("omega", C.c_double), ("mode", C.c_int), ("free_mask", C.c_uint),
+                ("mass", C.c_double), ("inertia", C.c_double), ("k", C.c_double * 3),
+                ("c", C.c_double * 3), ("q0", C.c_double * 3), ("f_ext", C.c_double * 3),
+                ("imp_amp", C.c_double), ("imp_freq", C.c_double), ("imp_y0", C.c_double),
+                ("smooth_delta", C.c_double), ("internal_mass_correction", C.c_int)]
+
+
+RECORD_DTYPE = np.dtype([("step", "<i8"), ("fvp", "<f8", (2,)), ("tvp", "<f8"),
+                         ("pin", "<f8", (3,)), ("fh", "<f8", (2,)), ("th", "<f8"),
+                         ("q", "<f8", (3,)), ("v", "<f8", (3,))])
+
+_LIB = None
+_DP = C.POINTER(C.c_double)
+
+
+def load_library(path=LIB_PATH):
+    """Load ``libvplbm.so``; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError("libvplbm.so is not built (run paper_1905_05110_amd.build)")
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.lbm_default_opts.argtypes = [C.POINTER(Opts)]
+    L.lbm_default_opts.restype = None
+    L.lbm_pop_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
+    L.lbm_pop_bytes.restype = C.c_size_t
+    L.lbm_create.argtypes = [C.c_int, C.c_int, Rates, C.c_double, C.POINTER(Opts), C.POINTER(P)]
+    L.lbm_set_body.argtypes = [P, C.POINTER(Body)]
+    L.lbm_clear_body.argtypes = [P]
+    L.lbm_step.argtypes = [P, C.c_int64]
+    L.lbm_set_graph_steps.argtypes = [P, C.c_int]
+    L.lbm_sync.argtypes = [P]
+    L.lbm_forces.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+    L.lbm_fields.argtypes = [P, _DP, _DP, _DP]
+    L.lbm_set_populations.argtypes = [P, _DP]
+    L.lbm_get_populations.argtypes = [P, _DP]
+    L.lbm_get_body_state.argtypes = [P, _DP, _DP]
+    L.lbm_step_index.argtypes = [P]
+    L.lbm_step_index.restype = C.c_int64
+    L.lbm_step_timed.argtypes = [P, C.c_int64, _DP, _DP]
+    L.lbm_save.argtypes = [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.lbm_load.argtypes = [P, C.c_void_p, C.c_size_t]
+    L.lbm_destroy.argtypes = [P]
+    L.lbm_last_error.argtypes = [P]
+    L.lbm_last_error.restype = C.c_char_p
+    _LIB = L
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+def make_opts(spec, stream=None, buffers=None, history_cap=65536):
+    L = load_library()
+    o = Opts()
+    L.lbm_default_opts(C.byref(o))
+    bc = spec.get("bc", ("periodic",) * 4)
+    for k in range(4):
+        o.bc[k] = BC[bc[k]] if isinstance(bc[k], str) else int(bc[k])
+    uw = spec.get("u_wall", [[0.0, 0.0]] * 4)
+    for k in range(4):
+        o.u_wall[k][0], o.u_wall[k][1] = float(uw[k][0]), float(uw[k][1])
+    o.u_conv = float(spec.get("u_conv", 0.0))
+    g = spec.get("g_fluid", (0.0, 0.0))
+    o.g_fluid[0], o.g_fluid[1] = float(g[0]), float(g[1])
+    o.rho0 = float(spec.get("rho0", 1.0))
+    u0 = spec.get("u0", (0.0, 0.0))
+    o.u0[0], o.u0[1] = float(u0[0]), float(u0[1])
+    st = spec.get("storage", "fp32")
+    o.storage = STORAGE[st] if isinstance(st, str) else int(st)
+    o.fp16_scale_log2 = int(spec.get("fp16_scale_log2", 10))
+    o.history_cap = int(history_cap)
+    o.hip_stream = stream
+    if buffers is not None:
+        o.pop_buffers[0], o.pop_buffers[1] = buffers
+    return o
+
+
+def make_body(body):
+    b = Body()
+    b.radius = float(body["radius"])
+    for name in ("x", "y", "theta", "vx", "vy", "omega"):
+        setattr(b, name, float(body.get(name, 0.0)))
+    m = body.get("mode", "fixed")
+    b.mode = MODE[m] if isinstance(m, str) else int(m)
+    b.free_mask = int(body.get("free_mask", 0))
+    b.mass = float(body.get("mass", 1.0))
+    b.inertia = float(body.get("inertia", 1.0))
+    for name in ("k", "c", "q0", "f_ext"):
+        vals = body.get(name, (0.0, 0.0, 0.0))
+        arr = getattr(b, name)
+        for d in range(3):
+            arr[d] = float(vals[d])
+    b.imp_amp = float(body.get("imp_amp", 0.0))
+    b.imp_freq = float(body.get("imp_freq", 0.0))
+    b.imp_y0 = float(body.get("imp_y0", body.get("y", 0.0)))
+    b.smooth_delta = float(body.get("smooth_delta", 0.0))
+    b.internal_mass_correction = int(body.get("internal_mass_correction", 1))
+    return b
+
+
+class Sim:
+    """One simulation on the current GPU.
+
+    ``torch_memory=True`` allocates the two population buffers as torch tensors and
+    runs on torch's current stream (the library then borrows them); otherwise the
+    library allocates its own buffers and stream.
+    """
+
+    def __init__(self, spec, body=None, torch_memory=False, history_cap=65536, graph_steps=0):
+        L = load_library()
+        self.L = L
+        self.spec = dict(spec)
+        self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
+        self._tensors = None
+        stream, buffers = None, None
+        if torch_memory:
+            import torch
+            st = spec.get("storage", "fp32")
+            nbytes = L.lbm_pop_bytes(self.nx, self.ny, STORAGE[st] if isinstance(st, str) else st)
+            self._tensors = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+            buffers = (self._tensors[0].data_ptr(), self._tensors[1].data_ptr())
+            stream = torch.cuda.current_stream().cuda_stream
+        o = make_opts(spec, stream, buffers, history_cap)
+        r = spec["rates"]
+        h = C.c_void_p()
+        rc = L.lbm_create(self.nx, self.ny, Rates(*[float(x) for x in r]), float(spec["eta"]),
+                          C.byref(o), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError(rc, L.lbm_last_error(None).decode())
+        self.h = h
+        if graph_steps:
+            self._check(L.lbm_set_graph_steps(self.h, int(graph_steps)))
+        if body is not None:
+            self.set_body(body)
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.L.lbm_last_error(self.h).decode())
+        return rc
+
+    def set_body(self, body):
+        self._body = make_body(body)
+        self._check(self.L.lbm_set_body(self.h, C.byref(self._body)))
+
+    def clear_body(self):
+        self._check(self.L.lbm_clear_body(self.h))
+
+    def step(self, n=1):
+        self._check(self.L.lbm_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.L.lbm_sync(self.h))
+
+    def set_graph_steps(self, k):
+        self._check(self.L.lbm_set_graph_steps(self.h, int(k)))
+
+    def forces(self, cap=None):
+        """Records of the steps not yet drained (structured array, oldest first)."""
+        if cap is None:
+            cap = max(self.step_index(), 1)
+        out = np.zeros(int(cap), dtype=RECORD_DTYPE)
+        n = C.c_int64()
+        self._check(self.L.lbm_forces(self.h, out.ctypes.data, int(cap), C.byref(n)))
+        return out[: n.value]
+
+    def fields(self):
+        rho = np.zeros((self.ny, self.nx))
+        ux, uy = np.zeros_like(rho), np.zeros_like(rho)
+        self._check(self.L.lbm_fields(self.h, _ptr(rho), _ptr(ux), _ptr(uy)))
+        return rho, ux, uy
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        self._check(self.L.lbm_set_populations(self.h, _ptr(f)))
+
+    def get_populations(self):
+        f = np.zeros((9, self.ny, self.nx))
+        self._check(self.L.lbm_get_populations(self.h, _ptr(f)))
+        return f
+
+    def body_state(self):
+        q, v = np.zeros(3), np.zeros(3)
+        self._check(self.L.lbm_get_body_state(self.h, _ptr(q), _ptr(v)))
+        return q, v
+
+    def step_index(self):
+        return int(self.L.lbm_step_index(self.h))
+
+    def step_timed(self, n):
+        k, r = C.c_double(), C.c_double()
+        self._check(self.L.lbm_step_timed(self.h, int(n), C.byref(k), C.byref(r)))
+        return k.value, r.value
+
+    def save(self):
+        size = C.c_size_t()
+        self._check(self.L.lbm_save(self.h, None, 0, C.byref(size)))
+        buf = np.zeros(size.value, dtype=np.uint8)
+        self._check(self.L.lbm_save(self.h, buf.ctypes.data, size.value, C.byref(size)))
+        return buf
+
+    def load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.L.lbm_load(self.h, buf.ctypes.data, buf.size))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_destroy(self.h)
+            self.h = None
+        self._tensors = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

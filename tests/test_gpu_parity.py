@@ -1,0 +1,279 @@
+"""GPU (HIP, through the C ABI) against the FP64 CPU oracle, element by element.
+
+Tolerances (relative, as defined for this project): populations and densities
+max|a - b| <= tol * max|b|; velocities max|a - b| <= tol * U; forces
+max_n |F_gpu(n) - F_orc(n)| <= tol * max_n |F_orc(n)|.  FP64 storage: tol = 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1905_05110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05110_amd import vplbm
+    vplbm.load_library()
+    return vplbm
+
+
+def spec_of(nx, ny, bc, tau=0.7, storage="fp64", g=(0.0, 0.0), u_wall=None, u_conv=0.0,
+            u0=(0.0, 0.0), rates=None):
+    return dict(nx=nx, ny=ny, rates=rates or (1.64, 1.54, 1.9, 1.0 / tau), eta=1e-3, bc=bc,
+                u_wall=u_wall or [[0.0, 0.0]] * 4, u_conv=u_conv, g_fluid=g, rho0=1.0, u0=u0,
+                storage=storage)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def force_err(ra, rb):
+    out = {}
+    for key in ("fvp", "tvp", "pin", "fh", "th"):
+        out[key] = rel(ra[key], rb[key])
+    out["q"] = np.abs(ra["q"] - rb["q"]).max()
+    out["v"] = np.abs(ra["v"] - rb["v"]).max()
+    return out
+
+
+BCS = {
+    "periodic": ("periodic",) * 4,
+    "channel": ("velocity", "outflow", "symmetry", "symmetry"),
+    "wallbox": ("wall",) * 4,
+    "symbox": ("symmetry",) * 4,
+    "mixed": ("velocity", "outflow", "wall", "velocity"),
+    "pipe": ("periodic", "periodic", "wall", "symmetry"),
+}
+UWALL = [[0.04, 0.01], [0.0, 0.0], [0.0, 0.0], [0.03, -0.005]]
+
+
+def body_of(kind, nx, ny, smooth):
+    D = min(nx, ny) * 0.45
+    b = W.fixed_disc(D, nx * 0.42 + 0.17, ny * 0.5 - 0.23, smooth_delta=1.0 if smooth else 0.0)
+    if kind == "fixed":
+        b.update(vx=0.002, omega=0.001)
+    elif kind == "imposed":
+        b.update(mode="imposed_sin", imp_amp=0.8, imp_freq=0.05, imp_y0=ny * 0.5 - 0.23)
+    elif kind == "free":
+        b.update(mode="free", free_mask=7, mass=400.0, inertia=3000.0, k=(0.01, 0.02, 0.0),
+                 c=(0.001, 0.0, 0.0), q0=(b["x"], b["y"], 0.0), f_ext=(1e-4, -2e-4, 0.0))
+    elif kind == "const_vel":
+        b.update(mode="const_vel", vx=0.03, vy=-0.02, omega=0.004)
+    return b
+
+
+def run_pair(gpu, spec, body, steps, seed, check_every=1, tol=1e-12, init_random=True):
+    from oracle import oracle as orc
+    nx, ny = spec["nx"], spec["ny"]
+    o = orc.OracleSim(spec, body)
+    g = gpu.Sim(spec, body)
+    if init_random:
+        f0 = W.random_populations(nx, ny, seed=seed, amp=0.05)
+        o.set_populations(f0)
+        g.set_populations(f0)
+    worst = 0.0
+    for s in range(0, steps, check_every):
+        n = min(check_every, steps - s)
+        ro = o.step(n)
+        g.step(n)
+        rg = g.forces()
+        fo, fg = o.get_populations(), g.get_populations()
+        e = rel(fg, fo)
+        worst = max(worst, e)
+        assert e <= tol, (s, e)
+        fe = force_err(rg, ro)
+        for key in ("fvp", "tvp", "pin", "fh", "th"):
+            if np.abs(ro[key]).max() > 1e-14:
+                assert fe[key] <= tol * 10, (s, key, fe)
+        assert fe["q"] <= 1e-12 * max(nx, ny) and fe["v"] <= 1e-12, (s, fe)
+    g.close()
+    return worst
+
+
+@pytest.mark.parametrize("bcname", list(BCS))
+@pytest.mark.parametrize("bodykind", ["none", "fixed", "imposed", "free", "const_vel"])
+@pytest.mark.parametrize("smooth", [False, True])
+def test_tiny_grids_step_by_step_fp64(gpu, bcname, bodykind, smooth):
+    if bodykind == "none" and smooth:
+        pytest.skip("no body")
+    nx, ny = 13, 11
+    _flush("tiny %s %s smooth=%s" % (bcname, bodykind, smooth))
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04,
+                   g=(2e-5, -1e-5) if bcname in ("periodic", "pipe") else (0.0, 0.0))
+    body = None if bodykind == "none" else body_of(bodykind, nx, ny, smooth)
+    run_pair(gpu, spec, body, steps=6, seed=1234)
+
+
+@pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
+def test_several_tiles_and_ragged_tail_fp64(gpu, bcname):
+    """nx = 600 spans three 256-wide tiles, the last one ragged; the body straddles
+    a tile border."""
+    nx, ny = 600, 24
+    _flush("ragged %s" % bcname)
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04)
+    b = W.fixed_disc(14.0, 256.3, 11.6)
+    b.update(mode="free", free_mask=7, mass=300.0, inertia=2000.0, k=(0.01, 0.01, 0.0),
+             q0=(256.3, 11.6, 0.0))
+    run_pair(gpu, spec, b, steps=8, seed=99, check_every=2)
+
+
+def test_circle_ties_are_classified_like_the_oracle(gpu):
+    """Disc of radius 10 centred on a node: the 12 nodes lying exactly on the circle
+    (d^2 == R^2) count as inside on both sides (317 nodes in all)."""
+    from oracle import oracle as orc
+    wl = W.imposed_oscillation()
+    spec = dict(wl["spec"], storage="fp64")
+    body = dict(wl["body"], mode="fixed")
+    o = orc.OracleSim(spec, body)
+    assert (o.chi_field()[0] > 0).sum() == 317
+    g = gpu.Sim(spec, body)
+    ro = o.step(3)
+    g.step(3)
+    rg = g.forces()
+    # chi * rho * u summed over the inside nodes: one misclassified node changes it
+    # by ~1/300 of its value
+    assert rel(rg["pin"], ro["pin"]) <= 1e-12
+    assert rel(rg["fvp"], ro["fvp"]) <= 1e-12
+    g.close()
+
+
+def test_imposed_oscillation_full_run_fp64(gpu):
+    """200x80 channel, imposed transverse oscillation, 2000 steps: every step's force
+    record and the final fields against the oracle."""
+    from oracle import oracle as orc
+    wl = W.imposed_oscillation(storage="fp64")
+    _flush("imposed oscillation fp64 2000 steps")
+    o = orc.OracleSim(wl["spec"], wl["body"])
+    g = gpu.Sim(wl["spec"], wl["body"])
+    ro = o.step(wl["steps"])
+    g.step(wl["steps"])
+    rg = g.forces()
+    assert len(rg) == wl["steps"]
+    assert (rg["step"] == np.arange(wl["steps"])).all()
+    fe = force_err(rg, ro)
+    assert fe["fvp"] <= 1e-12 and fe["tvp"] <= 1e-12 and fe["pin"] <= 1e-12, fe
+    assert fe["fh"] <= 1e-11, fe
+    assert fe["q"] <= 1e-12, fe
+    rho_o, ux_o, uy_o = o.fields()
+    rho_g, ux_g, uy_g = g.fields()
+    U0 = wl["U0"]
+    assert rel(rho_g, rho_o) <= 1e-12
+    assert np.abs(ux_g - ux_o).max() <= 1e-12 * U0
+    assert np.abs(uy_g - uy_o).max() <= 1e-12 * U0
+    g.close()
+
+
+def test_imposed_oscillation_fp32_velocity(gpu):
+    """FP32 storage and arithmetic: velocity after the 2000-step run within 1e-5 U0."""
+    from oracle import oracle as orc
+    wl = W.imposed_oscillation(storage="fp32")
+    _flush("imposed oscillation fp32")
+    o = orc.OracleSim(wl["spec"], wl["body"])
+    g = gpu.Sim(wl["spec"], wl["body"])
+    ro = o.step(wl["steps"])
+    g.step(wl["steps"])
+    rg = g.forces()
+    rho_o, ux_o, uy_o = o.fields()
+    rho_g, ux_g, uy_g = g.fields()
+    U0 = wl["U0"]
+    eu = max(np.abs(ux_g - ux_o).max(), np.abs(uy_g - uy_o).max()) / U0
+    ef = rel(rg["fvp"], ro["fvp"])
+    _flush("fp32: velocity err %.3e U0, force err %.3e" % (eu, ef))
+    assert eu <= 1e-5
+    assert ef <= 1e-4
+    g.close()
+
+
+def test_graph_replay_is_bitwise_equal_to_eager(gpu):
+    wl = W.imposed_oscillation(storage="fp32")
+    a = gpu.Sim(wl["spec"], wl["body"])
+    b = gpu.Sim(wl["spec"], wl["body"], graph_steps=8)
+    a.step(3)
+    b.step(3)  # odd start: one eager step, then graphs
+    a.step(37)
+    b.step(37)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    ra, rb = a.forces(), b.forces()
+    assert np.array_equal(ra["fvp"], rb["fvp"]) and np.array_equal(ra["q"], rb["q"])
+    a.close()
+    b.close()
+
+
+def test_save_and_load_resume_bitwise(gpu):
+    wl = W.imposed_oscillation(storage="fp32")
+    a = gpu.Sim(wl["spec"], wl["body"])
+    a.step(50)
+    blob = a.save()
+    a.step(30)
+    ref = a.get_populations()
+    rref = a.forces()[-30:]
+    b = gpu.Sim(wl["spec"], wl["body"])
+    b.load(blob)
+    b.step(30)
+    assert np.array_equal(b.get_populations(), ref)
+    rb = b.forces()
+    assert np.array_equal(rb["fvp"][-30:], rref["fvp"])
+    a.close()
+    b.close()
+
+
+def test_torch_memory_and_stream(gpu):
+    import torch
+    wl = W.imposed_oscillation(storage="fp32")
+    a = gpu.Sim(wl["spec"], wl["body"])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = gpu.Sim(wl["spec"], wl["body"], torch_memory=True)
+        b.step(40)
+    a.step(40)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    a.close()
+    b.close()
+
+
+def test_instability_is_reported(gpu):
+    spec = spec_of(16, 12, BCS["periodic"], tau=0.7)
+    g = gpu.Sim(spec, None)
+    f = W.random_populations(16, 12, seed=3)
+    f[:, 5, 5] = np.nan
+    g.set_populations(f)
+    g.step(2)
+    with pytest.raises(gpu.LbmError) as e:
+        g.sync()
+    assert e.value.code == gpu.LBM_ERR_UNSTABLE
+    g.close()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_full_size_free_viv_first_steps(gpu, storage):
+    """The 2048x1024 free-VIV grid in the launch configuration of the benchmark:
+    20 full steps against the oracle."""
+    from oracle import oracle as orc
+    wl = W.free_viv(storage=storage)
+    _flush("full size free viv %s" % storage)
+    o = orc.OracleSim(wl["spec"], wl["body"])
+    g = gpu.Sim(wl["spec"], wl["body"])
+    ro = o.step(20)
+    g.step(20)
+    rg = g.forces()
+    rho_o, ux_o, uy_o = o.fields()
+    rho_g, ux_g, uy_g = g.fields()
+    tol = 1e-12 if storage == "fp64" else 1e-5
+    U0 = wl["U0"]
+    assert max(np.abs(ux_g - ux_o).max(), np.abs(uy_g - uy_o).max()) <= tol * U0
+    assert rel(rho_g, rho_o) <= tol
+    assert rel(rg["fvp"], ro["fvp"]) <= (1e-12 if storage == "fp64" else 1e-4)
+    g.close()
