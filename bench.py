@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one device copy of 256 MiB first (scale for HBM byte counters)")
     ap.add_argument("--traffic", default=None,
                     help="JSON with measured HBM bytes per launch of the step kernel")
     return ap.parse_args()
@@ -70,6 +72,12 @@ def main():
     wl = W.free_viv(storage=args.storage)
     spec, body = wl["spec"], wl["body"]
     nodes = spec["nx"] * spec["ny"]
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         sim = vplbm.Sim(spec, body, torch_memory=True, history_cap=1 << 17,

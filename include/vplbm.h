@@ -56,11 +56,17 @@ enum {
 };
 
 /* Storage of the populations in device memory.  All forms store the offset
- * g = f - w_a from the rest-state weights; arithmetic is FP64 for LBM_FP64 and FP32
- * otherwise; force/torque reductions and the rigid body are always FP64.
+ * g = f - f_ref from a reference equilibrium (see lbm_opts.offset_ref); arithmetic is
+ * FP64 for LBM_FP64 and FP32 otherwise; force/torque reductions and the rigid body
+ * are always FP64.
  * LBM_FP16_OFS stores round-to-nearest-even(g * 2^k) as IEEE binary16 (k =
  * fp16_scale_log2); LBM_BF16_OFS stores round-to-nearest-even(g) as bfloat16. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
+
+/* Reference equilibrium of the stored offsets: INITIAL uses f_eq(1, u0) (the initial
+ * or inflow state, so a uniform stream is stored as zeros); REST uses the rest-state
+ * weights w_a = f_eq(1, 0). */
+enum { LBM_REF_INITIAL = 0, LBM_REF_REST = 1 };
 
 /* Boundary rule of one domain side (Sec. 3.1 for the channel set-up).
  *   PERIODIC  wrap around (both opposite sides must be periodic);
@@ -100,6 +106,9 @@ typedef struct {
     int storage;           /* LBM_FP64 / LBM_FP32 / LBM_FP16_OFS / LBM_BF16_OFS */
     int fp16_scale_log2;   /* k of the FP16 offset scale 2^k, 0..14 (default 10) */
     int history_cap;       /* force records kept on the device between drains (default 65536) */
+    int offset_ref;        /* LBM_REF_INITIAL (default) or LBM_REF_REST */
+    int rows_per_tile;     /* grid rows per 256-column tile (nodes per lane): 1, 2, 4, 8;
+                              0 = default.  Results do not depend on it. */
     void* hip_stream;      /* hipStream_t to run on; NULL: the library creates one */
     void* pop_buffers[2];  /* optional caller-owned device buffers of lbm_pop_bytes() each */
 } lbm_opts;
@@ -114,7 +123,8 @@ typedef struct {
     double smooth_delta;                       /* 0: sharp chi (d^2 <= R^2); > 0: chi =
                                                   1/(1 + exp(2 (d - R)/delta)), 0 beyond
                                                   d - R > 20 delta, 1 below -20 delta */
-    int internal_mass_correction;              /* FREE bodies use F_vp + dP_in/dt if set */
+    int internal_mass_correction;              /* 1: fh includes the internal-momentum
+                                                  change (see lbm_force_rec) */
 } lbm_body;
 
 /* Per-step record, written on the device for every step. */
@@ -122,9 +132,14 @@ typedef struct {
     int64_t step;      /* index of the step */
     double fvp[2];     /* sum over nodes of rho chi/eta (u - u_s): force on the body */
     double tvp;        /* its torque about the body centre */
-    double pin[3];     /* momentum and angular momentum of the fluid weighted by chi */
-    double fh[2], th;  /* force/torque driving a FREE body: fvp + (pin - pin_prev) when
-                          internal_mass_correction is set (zero on the first step) */
+    double pin[3];     /* post-collision momentum and angular momentum of the fluid inside
+                          the body: sum chi (j + G), sum chi r x (j + G) */
+    double fh[2], th;  /* hydrodynamic force/torque, fvp + pin(n) - pin(n-1) when
+                          internal_mass_correction is set (else fvp): for a sharp chi the
+                          momentum streamed across the interface (the momentum-exchange
+                          force of Eqs. (25)-(27)); FREE bodies are driven by it.  On the
+                          first step after lbm_set_body, pin(n-1) is the pre-collision
+                          momentum inside the body, sum chi j. */
     double q[3], v[3]; /* pose (x, y, theta) and velocities during this step */
 } lbm_force_rec;
 

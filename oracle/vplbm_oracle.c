@@ -85,7 +85,8 @@ typedef struct {
 typedef struct {
     int64_t step;
     double fvp[2], tvp;   /* penalization force and torque on the body */
-    double pin[3];        /* momentum and angular momentum of the fluid inside the body */
+    double pin[3];        /* post-collision momentum and angular momentum of the fluid
+                             inside the body: sum of chi * (j + G) and chi * r x (j + G) */
     double fh[2], th;     /* hydrodynamic force/torque (with the internal-fluid term when enabled) */
     double q[3], v[3];    /* pose and velocities used during this step */
 } orc_record;
@@ -376,15 +377,20 @@ void orc_body_advance(const orc_params* p, orc_body* b, const double* F) {
 int orc_step(const orc_params* p, const double* fin, double* fout, double* outlet, orc_body* b,
              orc_record* rec, int64_t step) {
     const int nx = p->nx, ny = p->ny;
-    double* rows = (double*)calloc((size_t)ny * 6, sizeof(double));
+    double* rows = (double*)calloc((size_t)ny * 9, sizeof(double));
     double* new_out = (double*)calloc((size_t)3 * ny, sizeof(double));
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j < ny; ++j) {
-        double acc[6] = {0, 0, 0, 0, 0, 0};
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int i = 0; i < nx; ++i) {
             double P[Q], out[Q], rho, ux, uy, G[2], dF[2], chi, usx, usy;
+            double jx = 0.0, jy = 0.0;
             for (int a = 0; a < Q; ++a) P[a] = pull(p, fin, outlet, a, i, j);
+            for (int a = 0; a < Q; ++a) {
+                jx += CX[a] * P[a];
+                jy += CY[a] * P[a];
+            }
             if (i == nx - 1 && p->bc[SIDE_E] == BC_OUTFLOW) {
                 new_out[0 * (size_t)ny + j] = P[3];
                 new_out[1 * (size_t)ny + j] = P[6];
@@ -398,15 +404,22 @@ int orc_step(const orc_params* p, const double* fin, double* fout, double* outle
             acc[0] += dF[0];
             acc[1] += dF[1];
             acc[2] += rx * dF[1] - ry * dF[0];
-            acc[3] += chi * rho * ux;
-            acc[4] += chi * rho * uy;
-            acc[5] += chi * rho * (rx * uy - ry * ux);
+            /* momentum inside the body after collision (j + G) and before it (j) */
+            double px = jx + G[0], py = jy + G[1];
+            acc[3] += chi * px;
+            acc[4] += chi * py;
+            acc[5] += chi * (rx * py - ry * px);
+            acc[6] += chi * jx;
+            acc[7] += chi * jy;
+            acc[8] += chi * (rx * jy - ry * jx);
+            (void)ux;
+            (void)uy;
         }
-        for (int k = 0; k < 6; ++k) rows[(size_t)j * 6 + k] = acc[k];
+        for (int k = 0; k < 9; ++k) rows[(size_t)j * 9 + k] = acc[k];
     }
-    double tot[6] = {0, 0, 0, 0, 0, 0};
+    double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int j = 0; j < ny; ++j)
-        for (int k = 0; k < 6; ++k) tot[k] += rows[(size_t)j * 6 + k];
+        for (int k = 0; k < 9; ++k) tot[k] += rows[(size_t)j * 9 + k];
     if (p->bc[SIDE_E] == BC_OUTFLOW) memcpy(outlet, new_out, sizeof(double) * 3 * (size_t)ny);
     free(rows);
     free(new_out);
@@ -419,10 +432,15 @@ int orc_step(const orc_params* p, const double* fin, double* fout, double* outle
     r.pin[0] = tot[3];
     r.pin[1] = tot[4];
     r.pin[2] = tot[5];
-    /* internal-fluid correction: F_h = F_vp + (P_in(n) - P_in(n-1)), zero on the first step */
+    /* Internal-fluid correction: F_h = F_vp + (P_in(n) - P_in(n-1)) with P_in the
+     * post-collision momentum inside the body.  For a sharp indicator this equals the
+     * momentum carried across the interface by streaming, i.e. the momentum-exchange
+     * force (Sec. 2.3, Eqs. (25)-(27)).  On the first step after the body is set,
+     * P_in(n-1) is taken as the momentum that streamed into the body (sum chi j). */
     double dp[3] = {0, 0, 0};
-    if (p->internal_mass_correction && b->pin_valid)
-        for (int d = 0; d < 3; ++d) dp[d] = r.pin[d] - b->pin_prev[d];
+    if (p->internal_mass_correction)
+        for (int d = 0; d < 3; ++d)
+            dp[d] = r.pin[d] - (b->pin_valid ? b->pin_prev[d] : tot[6 + d]);
     r.fh[0] = r.fvp[0] + dp[0];
     r.fh[1] = r.fvp[1] + dp[1];
     r.th = r.tvp + dp[2];

@@ -22,13 +22,13 @@ using namespace vplbm;
 // ---------------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------------
-template <class S>
+template <class S, int ROWS>
 __global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ dp, int p) {
     const SimDesc& d = *dp;
-    step_tile<S>(d, xcd_tile((int)blockIdx.x, (int)gridDim.x), p);
+    step_tile<S, ROWS>(d, xcd_tile((int)blockIdx.x, (int)gridDim.x), p);
 }
 
-// Fill both buffers' planes with constant offsets (initial equilibrium).
+// Fill one buffer's planes with constant offsets (initial equilibrium).
 template <class S>
 __global__ void k_fill(SimDesc d, double g0, double g1, double g2, double g3, double g4, double g5,
                        double g6, double g7, double g8, int buf) {
@@ -37,9 +37,9 @@ __global__ void k_fill(SimDesc d, double g0, double g1, double g2, double g3, do
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     const double g[NQ] = {g0, g1, g2, g3, g4, g5, g6, g7, g8};
-    S* f = reinterpret_cast<S*>(d.pop[buf]);
-    const long long base = (long long)j * d.pitch + i;
-    for (int a = 0; a < NQ; ++a) Codec<S>::store(f, a * d.ps + base, (T)g[a], d.scale);
+    const unsigned off = node_off<S>(d, i, j);
+    for (int a = 0; a < NQ; ++a)
+        Codec<S>::store(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)g[a], d.scale);
 }
 
 // Host FP64 populations f [9][ny][nx] <-> stored offsets.
@@ -49,14 +49,11 @@ __global__ void k_set_pop(SimDesc d, const double* __restrict__ f, int buf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
-    S* dst = reinterpret_cast<S*>(d.pop[buf]);
-    const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    const long long base = (long long)j * d.pitch + i;
-    const long long plane = (long long)d.nx * d.ny;
+    const long long plane_n = (long long)d.nx * d.ny;
+    const unsigned off = node_off<S>(d, i, j);
     for (int a = 0; a < NQ; ++a) {
-        const double v = f[a * plane + (long long)j * d.nx + i] - w[a];
-        Codec<S>::store(dst, a * d.ps + base, (T)v, d.scale);
+        const double v = f[a * plane_n + (long long)j * d.nx + i] - d.fref[a];
+        Codec<S>::store(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)v, d.scale);
     }
 }
 
@@ -65,14 +62,11 @@ __global__ void k_get_pop(SimDesc d, double* __restrict__ f, int buf) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
-    const S* src = reinterpret_cast<const S*>(d.pop[buf]);
-    const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    const long long base = (long long)j * d.pitch + i;
-    const long long plane = (long long)d.nx * d.ny;
+    const long long plane_n = (long long)d.nx * d.ny;
+    const unsigned off = node_off<S>(d, i, j);
     for (int a = 0; a < NQ; ++a)
-        f[a * plane + (long long)j * d.nx + i] =
-            (double)Codec<S>::load(src, a * d.ps + base, d.inv_scale) + w[a];
+        f[a * plane_n + (long long)j * d.nx + i] =
+            (double)Codec<S>::load(plane<S>(d, d.pop[buf], a), off, d.inv_scale) + d.fref[a];
 }
 
 // Density and penalized velocity of the current state, body at its current pose.
@@ -82,24 +76,24 @@ __global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= d.nx) return;
-    const S* fin = reinterpret_cast<const S*>(d.pop[p]);
     T g[NQ];
-    pull_node<S>(d, fin, i, j, g, false);
+    pull_edge<S>(d, d.pop[p], i, j, g, false);
     const BodyDev& B = *d.body;
-    double chi = 0.0, usx = 0.0, usy = 0.0;
+    double chi = 0.0, dsx = 0.0, dsy = 0.0;
     if (B.active) {
         const double rx = (double)i - B.q[p][0], ry = (double)j - B.q[p][1];
         chi = disc_chi(B, disc_d2(rx, ry));
-        usx = B.v[p][0] - B.v[p][2] * ry;
-        usy = B.v[p][1] + B.v[p][2] * rx;
+        if (chi > 0.0) {
+            dsx = (B.v[p][0] - B.v[p][2] * ry) - d.u0x;
+            dsy = (B.v[p][1] + B.v[p][2] * rx) - d.u0y;
+        }
     }
-    T drho, jx, jy, Gx, Gy;
     NodeOut<T> o;
-    macros<T>(d, g, (T)chi, (T)usx, (T)usy, drho, jx, jy, o, Gx, Gy);
-    const long long plane = (long long)d.nx * d.ny, o_ = (long long)j * d.nx + i;
+    macros<T>(consts_of<T>(d), g, (T)chi, (T)dsx, (T)dsy, o);
+    const long long plane_n = (long long)d.nx * d.ny, o_ = (long long)j * d.nx + i;
     out[o_] = (double)o.rho;
-    out[plane + o_] = (double)o.ux;
-    out[2 * plane + o_] = (double)o.uy;
+    out[plane_n + o_] = d.u0x + (double)o.dux;
+    out[2 * plane_n + o_] = d.u0y + (double)o.duy;
 }
 
 // ---------------------------------------------------------------------------------
@@ -152,6 +146,7 @@ struct lbm_sim {
     BodyDev body_h{};
     std::string err;
     int graph_steps = 0;
+    int rows = 4;  // rows of a tile (nodes per lane)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -182,14 +177,15 @@ static int dispatch(int storage, F&& f) {
     }
 }
 
-// Offsets of the equilibrium f_eq(rho, u) - w (Eq. (11)), evaluated in FP64.
-static void eq_offsets(double rho, double ux, double uy, double g[NQ]) {
-    static const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const double kW[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// Equilibrium f_eq(rho, u) (Eq. (11)) in FP64.
+static void equilibrium(double rho, double ux, double uy, double f[NQ]) {
     const double usq = ux * ux + uy * uy;
     for (int a = 0; a < NQ; ++a) {
         const double cu = dir_cx(a) * ux + dir_cy(a) * uy;
-        g[a] = w[a] * (rho - 1.0) + w[a] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        f[a] = kW[a] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
     }
 }
 
@@ -206,15 +202,24 @@ static void drop_graph(lbm_sim* s) {
     s->graph = nullptr;
 }
 
+template <class S>
+static void launch_rows(lbm_sim* s, int ntiles, int p) {
+    switch (s->rows) {
+        case 1: hipLaunchKernelGGL((k_step<S, 1>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
+        case 8: hipLaunchKernelGGL((k_step<S, 8>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
+        default: hipLaunchKernelGGL((k_step<S, 4>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
+    }
+}
+
 static int launch_step(lbm_sim* s) {
     const int p = (int)(s->host_step & 1);
     const int ntiles = s->desc.tiles_x * s->desc.tiles_y;
-    int rc = dispatch(s->storage, [&](auto* tag) {
+    dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_step<S>, dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p);
+        launch_rows<S>(s, ntiles, p);
         return LBM_OK;
     });
-    if (rc) return rc;
     HIP_TRY(s, hipGetLastError());
     s->host_step += 1;
     return LBM_OK;
@@ -261,6 +266,11 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
     if (o.storage == LBM_FP16_OFS && (o.fp16_scale_log2 < 0 || o.fp16_scale_log2 > 14))
         return m = "fp16_scale_log2 must lie in 0..14", LBM_ERR_ARG;
     if (o.history_cap < 1) return m = "history_cap must be >= 1", LBM_ERR_ARG;
+    if (o.rows_per_tile != 0 && o.rows_per_tile != 1 && o.rows_per_tile != 2 &&
+        o.rows_per_tile != 4 && o.rows_per_tile != 8)
+        return m = "rows_per_tile must be 0, 1, 2, 4 or 8", LBM_ERR_ARG;
+    if (o.offset_ref != LBM_REF_INITIAL && o.offset_ref != LBM_REF_REST)
+        return m = "unknown offset reference", LBM_ERR_ARG;
     if (!(o.rho0 > 0.0)) return m = "rho0 must be > 0", LBM_ERR_ARG;
     if ((o.pop_buffers[0] == nullptr) != (o.pop_buffers[1] == nullptr))
         return m = "pass both population buffers or neither", LBM_ERR_ARG;
@@ -334,11 +344,13 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
         CREATE_TRY(hipMalloc(&s->pop[1], s->pop_bytes));
     }
     const size_t tsz = o.storage == LBM_FP64 ? 8 : 4;
+    s->rows = o.rows_per_tile ? o.rows_per_tile : 4;
     const int tiles_x = (nx + TILE_X - 1) / TILE_X;
-    const int ntiles = tiles_x * ny;
+    const int tiles_y = (ny + s->rows - 1) / s->rows;
+    const int ntiles = tiles_x * tiles_y;
     CREATE_TRY(hipMalloc(&s->outlet, 3 * (size_t)ny * tsz));
     CREATE_TRY(hipMalloc((void**)&s->body_d, sizeof(BodyDev)));
-    CREATE_TRY(hipMalloc((void**)&s->partials, (size_t)ntiles * 6 * sizeof(double)));
+    CREATE_TRY(hipMalloc((void**)&s->partials, (size_t)ntiles * NRED * sizeof(double)));
     CREATE_TRY(hipMalloc((void**)&s->counter, 64));
     CREATE_TRY(hipMalloc((void**)&s->hist, (size_t)s->hist_cap * sizeof(Record)));
     CREATE_TRY(hipMalloc((void**)&s->flag, 64));
@@ -358,24 +370,49 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.nx = nx;
     d.ny = ny;
     d.pitch = row_pitch(nx);
+    d.rows = s->rows;
     d.tiles_x = tiles_x;
-    d.tiles_y = ny;
+    d.tiles_y = tiles_y;
     d.hist_cap = s->hist_cap;
     for (int k = 0; k < 4; ++k) d.bc[k] = o.bc[k];
-    d.s_e = rates.s_e;
-    d.s_eps = rates.s_eps;
-    d.s_q = rates.s_q;
-    d.s_nu = rates.s_nu;
-    d.inv_eta = 1.0 / eta;
-    d.gx = o.g_fluid[0];
-    d.gy = o.g_fluid[1];
-    d.u_conv = o.u_conv;
-    static const double w[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                                 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    // reference state of the stored offsets
+    const bool ref_rest = o.offset_ref == LBM_REF_REST;
+    d.u0x = ref_rest ? 0.0 : o.u0[0];
+    d.u0y = ref_rest ? 0.0 : o.u0[1];
+    equilibrium(1.0, d.u0x, d.u0y, d.fref);
+    Consts<double>& cd = d.cd;
+    cd.s_e = rates.s_e;
+    cd.s_eps = rates.s_eps;
+    cd.s_q = rates.s_q;
+    cd.s_nu = rates.s_nu;
+    cd.h_e = 1.0 - 0.5 * rates.s_e;
+    cd.h_eps = 1.0 - 0.5 * rates.s_eps;
+    cd.h_q = 1.0 - 0.5 * rates.s_q;
+    cd.h_nu = 1.0 - 0.5 * rates.s_nu;
+    cd.inv_eta = 1.0 / eta;
+    cd.gx = o.g_fluid[0];
+    cd.gy = o.g_fluid[1];
+    cd.u0x = d.u0x;
+    cd.u0y = d.u0y;
+    cd.uc = o.u_conv;
+    cd.inv1uc = 1.0 / (1.0 + o.u_conv);
+    for (int a = 0; a < NQ; ++a)
+        for (int b = 0; b < NQ; ++b) cd.dref[a][b] = d.fref[b] - d.fref[a];
     for (int side = 0; side < 4; ++side)
-        for (int a = 0; a < NQ; ++a)
-            d.bbc[side][a] =
-                6.0 * w[a] * (dir_cx(a) * o.u_wall[side][0] + dir_cy(a) * o.u_wall[side][1]);
+        for (int a = 0; a < NQ; ++a) {
+            const double moving =
+                o.bc[side] == LBM_BC_VELOCITY
+                    ? 6.0 * kW[a] * (dir_cx(a) * o.u_wall[side][0] + dir_cy(a) * o.u_wall[side][1])
+                    : 0.0;
+            cd.bb[side][a] = moving + cd.dref[a][dir_opp(a)];
+        }
+    Consts<float>& cf = d.cf;
+    {
+        const double* src = reinterpret_cast<const double*>(&cd);
+        float* dst = reinterpret_cast<float*>(&cf);
+        static_assert(sizeof(Consts<double>) == 2 * sizeof(Consts<float>), "constant blocks");
+        for (size_t k = 0; k < sizeof(Consts<double>) / sizeof(double); ++k) dst[k] = (float)src[k];
+    }
     if (o.storage == LBM_FP16_OFS) {
         d.scale = std::ldexp(1.0f, o.fp16_scale_log2);
         d.inv_scale = std::ldexp(1.0f, -o.fp16_scale_log2);
@@ -390,7 +427,8 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     CREATE_TRY(hipMemsetAsync(s->counter, 0, 64, s->stream));
     CREATE_TRY(hipMemsetAsync(s->flag, 0, 64, s->stream));
     double g[NQ];
-    eq_offsets(o.rho0, o.u0[0], o.u0[1], g);
+    equilibrium(o.rho0, o.u0[0], o.u0[1], g);
+    for (int a = 0; a < NQ; ++a) g[a] -= d.fref[a];
     dispatch(o.storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         for (int b = 0; b < 2; ++b)

@@ -1,9 +1,12 @@
 // vplbm_device.hpp -- device-side data structures and per-node arithmetic of the
 // VP-LBM time step for gfx950 (MI355X).
 //
-// Populations are held as offsets g = f - w_a from the rest-state weights in every
-// storage precision; the moment transform below works on the offsets directly,
-// using M w = (1, -2, 1, 0, ..., 0) (the equilibrium moments of rho = 1, u = 0).
+// Populations are held as offsets g = f - f_ref from a reference equilibrium
+// f_ref = f_eq(1, u_ref) in every storage precision (u_ref = 0 gives the rest-state
+// weights w_a).  The moment transform works on the offsets directly, using
+// M f_ref = m_eq(1, u_ref), and the macroscopic velocity is carried as du = u - u_ref,
+// so that a flow near the reference state is stored and updated without cancelling
+// against u_ref.
 // Method: Liberge & Beghein (arXiv 1905.05110), Sec. 2.1-2.3 and Algorithm 1.
 #pragma once
 
@@ -13,8 +16,11 @@
 namespace vplbm {
 
 constexpr int NQ = 9;
-constexpr int TILE_X = 256;  // nodes of one row handled by a workgroup (one per lane)
+constexpr int TILE_X = 256;  // columns of a tile: one per lane of a 256-thread workgroup
 constexpr int NWAVE = TILE_X / 64;
+// per-step FP64 sums: penalization force (2) and torque (1); momentum inside the body
+// after collision (2 + 1 angular) and before it (2 + 1)
+constexpr int NRED = 9;
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_SYMMETRY = 3, BC_OUTFLOW = 4 };
 enum { MODE_FIXED = 0, MODE_IMPOSED_SIN = 1, MODE_FREE = 2, MODE_CONST_VEL = 3 };
@@ -79,26 +85,47 @@ struct Record {  // same layout as lbm_force_rec
     double fvp[2], tvp, pin[3], fh[2], th, q[3], v[3];
 };
 
+// Per-simulation constants in the arithmetic precision T, precomputed on the host.
+template <class T>
+struct Consts {
+    T s_e, s_eps, s_q, s_nu;      // MRT rates of the non-conserved moments
+    T h_e, h_eps, h_q, h_nu;      // 1 - s/2 (source weights of Eq. (8))
+    T inv_eta, gx, gy, u0x, u0y;  // 1/eta, fluid body force, reference velocity
+    T uc, inv1uc;                 // convective outflow velocity, 1/(1 + U_c)
+    T bb[4][NQ];                  // bounce-back increment per side and direction
+    T dref[NQ][NQ];               // f_ref[b] - f_ref[a]: correction when a pulls b
+};
+
 struct SimDesc {
     void* pop[2];        // two population buffers, 9 planes of ps elements each
     void* outlet;        // 3 x ny offsets (directions 3, 6, 7) of the outflow memory
     BodyDev* body;
-    double* partials;    // 6 FP64 sums per participating workgroup
-    unsigned* counter;   // arrival counter of the participating workgroups
+    double* partials;    // NRED FP64 sums per participating tile
+    unsigned* counter;   // arrival counter of the participating tiles
     Record* hist;        // ring of per-step records
     int* flag;           // set to 1 when an unstable node is met
     long long ps;        // plane stride (elements)
-    int nx, ny, pitch, tiles_x, tiles_y, hist_cap;
+    int nx, ny, pitch, rows, tiles_x, tiles_y, hist_cap, pad;
     int bc[4];
-    double s_e, s_eps, s_q, s_nu;
-    double inv_eta;
-    double gx, gy;
-    double u_conv;
-    double bbc[4][NQ];   // moving-wall increments 6 w_a (c_a . u_wall) per side
+    double u0x, u0y;     // reference velocity u_ref of the offsets
+    double fref[NQ];     // f_eq(1, u_ref)
     float scale, inv_scale;  // storage scale of 16-bit offsets
+    Consts<double> cd;
+    Consts<float> cf;
 };
 
-// ---- storage codecs -----------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ const Consts<T>& consts_of(const SimDesc& d);
+template <>
+__device__ __forceinline__ const Consts<double>& consts_of<double>(const SimDesc& d) {
+    return d.cd;
+}
+template <>
+__device__ __forceinline__ const Consts<float>& consts_of<float>(const SimDesc& d) {
+    return d.cf;
+}
+
+// ---- storage codecs (byte offsets from a plane base) -----------------------------------
 struct bf16s {
     uint16_t bits;
 };
@@ -109,18 +136,22 @@ struct Codec;
 template <>
 struct Codec<double> {
     using T = double;
-    static __device__ __forceinline__ T load(const double* p, long long i, float) { return p[i]; }
-    static __device__ __forceinline__ void store(double* p, long long i, T v, float) {
-        __builtin_nontemporal_store(v, p + i);
+    static __device__ __forceinline__ T load(const char* base, unsigned off, float) {
+        return *reinterpret_cast<const double*>(base + off);
+    }
+    static __device__ __forceinline__ void store(char* base, unsigned off, T v, float) {
+        __builtin_nontemporal_store(v, reinterpret_cast<double*>(base + off));
     }
 };
 
 template <>
 struct Codec<float> {
     using T = float;
-    static __device__ __forceinline__ T load(const float* p, long long i, float) { return p[i]; }
-    static __device__ __forceinline__ void store(float* p, long long i, T v, float) {
-        __builtin_nontemporal_store(v, p + i);
+    static __device__ __forceinline__ T load(const char* base, unsigned off, float) {
+        return *reinterpret_cast<const float*>(base + off);
+    }
+    static __device__ __forceinline__ void store(char* base, unsigned off, T v, float) {
+        __builtin_nontemporal_store(v, reinterpret_cast<float*>(base + off));
     }
 };
 
@@ -128,11 +159,11 @@ template <>
 struct Codec<_Float16> {
     using T = float;
     // stored value: round-to-nearest-even of g * 2^k
-    static __device__ __forceinline__ T load(const _Float16* p, long long i, float inv_scale) {
-        return (float)p[i] * inv_scale;
+    static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
+        return (float)*reinterpret_cast<const _Float16*>(base + off) * inv_scale;
     }
-    static __device__ __forceinline__ void store(_Float16* p, long long i, T v, float scale) {
-        __builtin_nontemporal_store((_Float16)(v * scale), p + i);
+    static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
+        __builtin_nontemporal_store((_Float16)(v * scale), reinterpret_cast<_Float16*>(base + off));
     }
 };
 
@@ -146,22 +177,33 @@ __host__ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 template <>
 struct Codec<bf16s> {
     using T = float;
-    static __device__ __forceinline__ T load(const bf16s* p, long long i, float inv_scale) {
-        const uint16_t b = reinterpret_cast<const uint16_t*>(p)[i];
+    static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
+        const uint16_t b = *reinterpret_cast<const uint16_t*>(base + off);
         return __builtin_bit_cast(float, (uint32_t)b << 16) * inv_scale;
     }
-    static __device__ __forceinline__ void store(bf16s* p, long long i, T v, float scale) {
-        __builtin_nontemporal_store(f32_to_bf16_rne(v * scale), reinterpret_cast<uint16_t*>(p) + i);
+    static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
+        __builtin_nontemporal_store(f32_to_bf16_rne(v * scale), reinterpret_cast<uint16_t*>(base + off));
     }
 };
+
+template <class S>
+__device__ __forceinline__ unsigned node_off(const SimDesc& d, int i, int j) {
+    return ((unsigned)j * (unsigned)d.pitch + (unsigned)i) * (unsigned)sizeof(S);
+}
+
+template <class S>
+__device__ __forceinline__ const char* plane(const SimDesc& d, const void* buf, int a) {
+    return reinterpret_cast<const char*>(buf) + (long long)a * d.ps * (long long)sizeof(S);
+}
 
 // ---- streaming with boundary rules (Eq. (18) applied as a pull) -----------------------
 // Value pulled by node (i, j) for direction a.  Returns false when the source crosses
 // an OUTFLOW side (the caller then applies the convective rule).
 template <class S>
-__device__ bool pull_rules(const SimDesc& d, const S* __restrict__ fin, int a, int i, int j,
+__device__ bool pull_rules(const SimDesc& d, const void* fin, int a, int i, int j,
                            typename Codec<S>::T& out) {
     using T = typename Codec<S>::T;
+    const Consts<T>& c = consts_of<T>(d);
     int dir = a;
     int si = i - dir_cx(a);
     int sj = j - dir_cy(a);
@@ -176,10 +218,8 @@ __device__ bool pull_rules(const SimDesc& d, const S* __restrict__ fin, int a, i
         } else if (kind == BC_OUTFLOW) {
             return false;
         } else {  // WALL or VELOCITY: half-way bounce-back of the population leaving (i, j)
-            T v = Codec<S>::load(fin, (long long)dir_opp(a) * d.ps + (long long)j * d.pitch + i,
-                                 d.inv_scale);
-            if (kind == BC_VELOCITY) v += (T)d.bbc[side][a];
-            out = v;
+            out = Codec<S>::load(plane<S>(d, fin, dir_opp(a)), node_off<S>(d, i, j), d.inv_scale) +
+                  c.bb[side][a];
             return true;
         }
     }
@@ -192,44 +232,27 @@ __device__ bool pull_rules(const SimDesc& d, const S* __restrict__ fin, int a, i
             dir = dir_flip_y(dir);
             sj = j;
         } else {
-            T v = Codec<S>::load(fin, (long long)dir_opp(a) * d.ps + (long long)j * d.pitch + i,
-                                 d.inv_scale);
-            if (kind == BC_VELOCITY) v += (T)d.bbc[side][a];
-            out = v;
+            out = Codec<S>::load(plane<S>(d, fin, dir_opp(a)), node_off<S>(d, i, j), d.inv_scale) +
+                  c.bb[side][a];
             return true;
         }
     }
-    out = Codec<S>::load(fin, (long long)dir * d.ps + (long long)sj * d.pitch + si, d.inv_scale);
+    out = Codec<S>::load(plane<S>(d, fin, dir), node_off<S>(d, si, sj), d.inv_scale);
+    if (dir != a) out += c.dref[a][dir];  // specular reflection between directions
     return true;
 }
 
 // Index of a direction in the 3-slot outflow memory (directions 3, 6, 7).
 __device__ __forceinline__ int outflow_slot(int a) { return a == 3 ? 0 : (a == 6 ? 1 : 2); }
 
-// All nine pulled offsets of node (i, j).  The interior fast path reads the nine
-// shifted planes directly; nodes on the domain edge go through the boundary rules.
-// When update_outlet is set, the east column stores its pulled values 3, 6, 7 as the
+// Pulled offsets of a node on the domain edge, through the boundary rules.  When
+// update_outlet is set, the east column stores its pulled values 3, 6, 7 as the
 // outflow memory of the next step.
 template <class S>
-__device__ __forceinline__ void pull_node(const SimDesc& d, const S* __restrict__ fin, int i, int j,
-                                          typename Codec<S>::T g[NQ], bool update_outlet) {
+__device__ void pull_edge(const SimDesc& d, const void* fin, int i, int j,
+                          typename Codec<S>::T g[NQ], bool update_outlet) {
     using T = typename Codec<S>::T;
-    const long long ps = d.ps;
-    const int pitch = d.pitch;
-    if (i >= 1 && i <= d.nx - 2 && j >= 1 && j <= d.ny - 2) {
-        const S* b = fin + (long long)j * pitch + i;
-        const float is = d.inv_scale;
-        g[0] = Codec<S>::load(b, 0, is);
-        g[1] = Codec<S>::load(b, 1 * ps - 1, is);
-        g[2] = Codec<S>::load(b, 2 * ps - pitch, is);
-        g[3] = Codec<S>::load(b, 3 * ps + 1, is);
-        g[4] = Codec<S>::load(b, 4 * ps + pitch, is);
-        g[5] = Codec<S>::load(b, 5 * ps - pitch - 1, is);
-        g[6] = Codec<S>::load(b, 6 * ps - pitch + 1, is);
-        g[7] = Codec<S>::load(b, 7 * ps + pitch + 1, is);
-        g[8] = Codec<S>::load(b, 8 * ps + pitch - 1, is);
-        return;
-    }
+    const Consts<T>& c = consts_of<T>(d);
     T* outlet = reinterpret_cast<T*>(d.outlet);
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
@@ -239,8 +262,7 @@ __device__ __forceinline__ void pull_node(const SimDesc& d, const S* __restrict_
             // last step's value at the east column and this step's value one node in
             T qv;
             pull_rules<S>(d, fin, a, d.nx - 2, j, qv);
-            const T uc = (T)d.u_conv;
-            v = (outlet[outflow_slot(a) * d.ny + j] + uc * qv) / (T(1) + uc);
+            v = (outlet[outflow_slot(a) * d.ny + j] + c.uc * qv) * c.inv1uc;
         }
         g[a] = v;
     }
@@ -249,6 +271,22 @@ __device__ __forceinline__ void pull_node(const SimDesc& d, const S* __restrict_
         outlet[1 * d.ny + j] = g[6];
         outlet[2 * d.ny + j] = g[7];
     }
+}
+
+// Interior node: the nine shifted planes are read directly (pull of Eq. (18)).
+template <class S>
+__device__ __forceinline__ void pull_interior(const char* const P[NQ], unsigned off, unsigned rowb,
+                                              float is, typename Codec<S>::T g[NQ]) {
+    constexpr unsigned e = sizeof(S);
+    g[0] = Codec<S>::load(P[0], off, is);
+    g[1] = Codec<S>::load(P[1], off - e, is);
+    g[2] = Codec<S>::load(P[2], off - rowb, is);
+    g[3] = Codec<S>::load(P[3], off + e, is);
+    g[4] = Codec<S>::load(P[4], off + rowb, is);
+    g[5] = Codec<S>::load(P[5], off - rowb - e, is);
+    g[6] = Codec<S>::load(P[6], off - rowb + e, is);
+    g[7] = Codec<S>::load(P[7], off + rowb + e, is);
+    g[8] = Codec<S>::load(P[8], off + rowb - e, is);
 }
 
 // ---- indicator function of the disc (Sec. 2.1, Eq. (2)) and rigid velocity ---------
@@ -269,9 +307,9 @@ __device__ __forceinline__ double disc_chi(const BodyDev& B, double d2) {
     return 1.0 / (1.0 + exp(2.0 * z));
 }
 
-// Tile range (inclusive) of the workgroups whose rows/columns meet the support of the
-// body; all its nodes with chi > 0 lie inside.  An absent or out-of-domain body maps
-// to tile (0, 0) alone, so that exactly one workgroup finalises every step.
+// Tile range (inclusive) of the tiles that meet the support of the body; all its
+// nodes with chi > 0 lie inside.  An absent or out-of-domain body maps to tile (0, 0)
+// alone, so that exactly one workgroup finalises every step.
 __device__ __forceinline__ void body_tiles(const SimDesc& d, const BodyDev& B, double X, double Y,
                                            int& tx0, int& tx1, int& ty0, int& ty1) {
     tx0 = tx1 = ty0 = ty1 = 0;
@@ -283,41 +321,57 @@ __device__ __forceinline__ void body_tiles(const SimDesc& d, const BodyDev& B, d
     if (!(xl <= xh) || !(yl <= yh)) return;
     tx0 = (int)xl / TILE_X;
     tx1 = (int)xh / TILE_X;
-    ty0 = (int)yl;
-    ty1 = (int)yh;
+    ty0 = (int)yl / d.rows;
+    ty1 = (int)yh / d.rows;
 }
 
 // ---- macroscopic quantities, penalized velocity and MRT collision ------------------
 template <class T>
 struct NodeOut {
-    T rho, ux, uy, dFx, dFy;
+    T rho, drho, dux, duy, ux, uy, dFx, dFy, jgx, jgy, Gx, Gy;
 };
+
+template <class T>
+__device__ __forceinline__ T recip(T x) {
+    return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);  // 1 ulp; FP32 arithmetic is not held to IEEE division
+}
 
 // Density, momentum and the implicit penalized velocity (Sec. 2.2, Eqs. (19)-(22)):
 //   rho (1 + lam/2) u = j + rho g/2 + rho lam u_s / 2,   lam = chi / eta,
 // solved for r = u - u_s; the fluid receives G = rho g - rho lam r and the body
-// rho lam r.
+// rho lam r.  With j = jg + u_ref (jg the momentum of the offsets) and
+// ds = u_s - u_ref:  r = (jg - drho u_ref + rho g/2 - rho ds) / (rho (1 + lam/2)),
+// u - u_ref = ds + r.  Where chi = 0 the result does not depend on u_s, and ds = 0
+// is passed so that no term cancels against u_ref.
 template <class T>
-__device__ __forceinline__ void macros(const SimDesc& d, const T g[NQ], T chi, T usx, T usy,
-                                       T& drho, T& jx, T& jy, NodeOut<T>& o, T& Gx, T& Gy) {
+__device__ __forceinline__ void macros(const Consts<T>& c, const T g[NQ], T chi, T dsx, T dsy,
+                                       NodeOut<T>& o) {
     const T s1234 = (g[1] + g[2]) + (g[3] + g[4]);
     const T s5678 = (g[5] + g[6]) + (g[7] + g[8]);
-    drho = g[0] + s1234 + s5678;
-    jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const T drho = g[0] + s1234 + s5678;
+    const T jgx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const T jgy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
     const T rho = T(1) + drho;
-    const T lam = chi * (T)d.inv_eta;
-    const T gx = (T)d.gx, gy = (T)d.gy;
-    const T inv = T(1) / (rho * (T(1) + T(0.5) * lam));
-    const T rx = (jx + T(0.5) * rho * gx - rho * usx) * inv;
-    const T ry = (jy + T(0.5) * rho * gy - rho * usy) * inv;
+    const T lam = chi * c.inv_eta;
+    const T inv = recip<T>(rho * (T(1) + T(0.5) * lam));
+    const T rx = (jgx - drho * c.u0x + T(0.5) * rho * c.gx - rho * dsx) * inv;
+    const T ry = (jgy - drho * c.u0y + T(0.5) * rho * c.gy - rho * dsy) * inv;
     o.rho = rho;
-    o.ux = usx + rx;
-    o.uy = usy + ry;
+    o.drho = drho;
+    o.dux = dsx + rx;
+    o.duy = dsy + ry;
+    o.ux = c.u0x + o.dux;
+    o.uy = c.u0y + o.duy;
     o.dFx = rho * lam * rx;
     o.dFy = rho * lam * ry;
-    Gx = rho * gx - o.dFx;
-    Gy = rho * gy - o.dFy;
+    o.Gx = rho * c.gx - o.dFx;
+    o.Gy = rho * c.gy - o.dFy;
+    o.jgx = jgx;
+    o.jgy = jgy;
 }
 
 // Collision in moment space with the forcing source (Eqs. (8), (14), (16), (17); the
@@ -326,10 +380,10 @@ __device__ __forceinline__ void macros(const SimDesc& d, const T g[NQ], T chi, T
 // are (0, 6 u.G, -6 u.G, Gx, -Gx, Gy, -Gy, 2(ux Gx - uy Gy), ux Gy + uy Gx).
 // The conserved moments come out as rho, j + G whatever their rates.
 template <class T>
-__device__ __forceinline__ void collide(const SimDesc& d, const T g[NQ], T chi, T usx, T usy,
+__device__ __forceinline__ void collide(const Consts<T>& c, const T g[NQ], T chi, T dsx, T dsy,
                                         T out[NQ], NodeOut<T>& o) {
-    T drho, jx, jy, Gx, Gy;
-    macros<T>(d, g, chi, usx, usy, drho, jx, jy, o, Gx, Gy);
+    macros<T>(c, g, chi, dsx, dsy, o);
+    const T drho = o.drho, Gx = o.Gx, Gy = o.Gy;
     const T s1234 = (g[1] + g[2]) + (g[3] + g[4]);
     const T s5678 = (g[5] + g[6]) + (g[7] + g[8]);
     // non-conserved moments of the offsets (M g)
@@ -342,26 +396,29 @@ __device__ __forceinline__ void collide(const SimDesc& d, const T g[NQ], T chi, 
     const T pxx = (g[1] + g[3]) - (g[2] + g[4]);
     const T pxy = (g[5] + g[7]) - (g[6] + g[8]);
 
-    const T rho = o.rho, ux = o.ux, uy = o.uy;
+    const T ux = o.ux, uy = o.uy, dux = o.dux, duy = o.duy;
+    const T u0x = c.u0x, u0y = c.u0y;
     const T usq = ux * ux + uy * uy;
-    // equilibria of the offsets (m_eq - M w)
-    const T e_eq = T(3) * rho * usq - T(2) * drho;
-    const T ep_eq = drho - T(3) * rho * usq;
-    const T qx_eq = -rho * ux;
-    const T qy_eq = -rho * uy;
-    const T pxx_eq = rho * (ux * ux - uy * uy);
-    const T pxy_eq = rho * ux * uy;
-    const T uG = ux * Gx + uy * Gy;
+    // equilibria of the offsets, m_eq(rho, u) - m_eq(1, u_ref), in terms of drho and du
+    const T dsqx = dux * (T(2) * u0x + dux);  // ux^2 - u0x^2
+    const T dsqy = duy * (T(2) * u0y + duy);
+    const T dE = drho * usq + (dsqx + dsqy);  // rho |u|^2 - |u_ref|^2
+    const T e_eq = T(3) * dE - T(2) * drho;
+    const T ep_eq = drho - T(3) * dE;
+    const T qx_eq = -(drho * ux + dux);
+    const T qy_eq = -(drho * uy + duy);
+    const T pxx_eq = drho * (ux * ux - uy * uy) + (dsqx - dsqy);
+    const T pxy_eq = drho * ux * uy + (dux * u0y + u0x * duy + dux * duy);
+    const T uG6 = T(6) * (ux * Gx + uy * Gy);
 
-    const T se = (T)d.s_e, sp = (T)d.s_eps, sq = (T)d.s_q, sn = (T)d.s_nu;
-    const T e_s = e - se * (e - e_eq) + (T(1) - T(0.5) * se) * (T(6) * uG);
-    const T ep_s = ep - sp * (ep - ep_eq) - (T(1) - T(0.5) * sp) * (T(6) * uG);
-    const T qx_s = qx - sq * (qx - qx_eq) - (T(1) - T(0.5) * sq) * Gx;
-    const T qy_s = qy - sq * (qy - qy_eq) - (T(1) - T(0.5) * sq) * Gy;
-    const T pxx_s = pxx - sn * (pxx - pxx_eq) + (T(1) - T(0.5) * sn) * (T(2) * (ux * Gx - uy * Gy));
-    const T pxy_s = pxy - sn * (pxy - pxy_eq) + (T(1) - T(0.5) * sn) * (ux * Gy + uy * Gx);
-    const T jx_s = jx + Gx;
-    const T jy_s = jy + Gy;
+    const T e_s = e - c.s_e * (e - e_eq) + c.h_e * uG6;
+    const T ep_s = ep - c.s_eps * (ep - ep_eq) - c.h_eps * uG6;
+    const T qx_s = qx - c.s_q * (qx - qx_eq) - c.h_q * Gx;
+    const T qy_s = qy - c.s_q * (qy - qy_eq) - c.h_q * Gy;
+    const T pxx_s = pxx - c.s_nu * (pxx - pxx_eq) + c.h_nu * (T(2) * (ux * Gx - uy * Gy));
+    const T pxy_s = pxy - c.s_nu * (pxy - pxy_eq) + c.h_nu * (ux * Gy + uy * Gx);
+    const T jx_s = o.jgx + Gx;
+    const T jy_s = o.jgy + Gy;
 
     // f = M^-1 m*, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
     const T a0 = drho * T(1.0 / 9.0);
@@ -374,7 +431,7 @@ __device__ __forceinline__ void collide(const SimDesc& d, const T g[NQ], T chi, 
     const T a7 = pxx_s * T(0.25);
     const T a8 = pxy_s * T(0.25);
     const T b = a0 - a1 - T(2) * a2;
-    const T c = a0 + T(2) * a1 + a2;
+    const T cc = a0 + T(2) * a1 + a2;
     const T x1 = a3 - T(2) * a4, y1 = a5 - T(2) * a6;
     const T x2 = a3 + a4, y2 = a5 + a6;
     out[0] = a0 - T(4) * a1 + T(4) * a2;
@@ -382,10 +439,10 @@ __device__ __forceinline__ void collide(const SimDesc& d, const T g[NQ], T chi, 
     out[2] = b + y1 - a7;
     out[3] = b - x1 + a7;
     out[4] = b - y1 - a7;
-    out[5] = c + x2 + y2 + a8;
-    out[6] = c - x2 + y2 - a8;
-    out[7] = c - x2 - y2 + a8;
-    out[8] = c + x2 - y2 - a8;
+    out[5] = cc + x2 + y2 + a8;
+    out[6] = cc - x2 + y2 - a8;
+    out[7] = cc - x2 - y2 + a8;
+    out[8] = cc + x2 - y2 - a8;
 }
 
 // ---- rigid body (Sec. 2.3, Eqs. (23)-(24); RK4 of Algorithm 1) -----------------------
@@ -403,8 +460,13 @@ __device__ __forceinline__ void rk4_dof(double Mq, double cq, double kq, double 
 }
 
 // Finalise one step: record it and advance the body (reads [p], writes [p ^ 1]).
-// tot = (F_vp x, y, T_vp, P_in x, y, theta).
-__device__ inline void body_advance(const SimDesc& d, int p, const double tot[6]) {
+// tot = (F_vp x, y, T_vp, P_in x, y, theta after collision, the same before it).
+// The hydrodynamic load is F_vp + P_in(n) - P_in(n-1): with P_in the post-collision
+// momentum inside the body this is, for a sharp indicator, the momentum carried
+// across the interface by streaming (the momentum-exchange force of Eqs. (25)-(27));
+// on the first step after the body is set the pre-collision momentum stands in for
+// P_in(n-1).
+__device__ inline void body_advance(const SimDesc& d, int p, const double tot[NRED]) {
     BodyDev& B = *d.body;
     Record r;
     r.step = B.step;
@@ -415,8 +477,8 @@ __device__ inline void body_advance(const SimDesc& d, int p, const double tot[6]
     r.pin[1] = tot[4];
     r.pin[2] = tot[5];
     double dp[3] = {0.0, 0.0, 0.0};
-    if (B.imc && B.pin_valid)
-        for (int k = 0; k < 3; ++k) dp[k] = tot[3 + k] - B.pin_prev[k];
+    if (B.imc)
+        for (int k = 0; k < 3; ++k) dp[k] = tot[3 + k] - (B.pin_valid ? B.pin_prev[k] : tot[6 + k]);
     r.fh[0] = tot[0] + dp[0];
     r.fh[1] = tot[1] + dp[1];
     r.th = tot[2] + dp[2];
@@ -471,62 +533,104 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 }
 
 // ---- one tile of one step ------------------------------------------------------------
-// Pull, penalize, collide and store a row segment of TILE_X nodes; workgroups that
-// meet the body reduce force, torque and internal momentum in FP64 into their slot;
-// the last of them to arrive sums the slots in fixed order and advances the body.
-template <class S>
+// A tile is TILE_X columns x ROWS rows; each lane walks down its column, issuing the
+// next row's nine loads before colliding the current row.  Nodes are pulled,
+// penalized, collided and stored; tiles that meet the body reduce force, torque and
+// internal momentum in FP64 into their slot, and the last of them to arrive sums the
+// slots in a fixed order and advances the body.
+template <class S, int ROWS>
 __device__ __forceinline__ void step_tile(const SimDesc& d, int tile, int p) {
     using T = typename Codec<S>::T;
-    __shared__ double red[NWAVE][6];
+    __shared__ double red[NWAVE][NRED];
     __shared__ int last;
-    const S* __restrict__ fin = reinterpret_cast<const S*>(d.pop[p]);
-    S* __restrict__ fout = reinterpret_cast<S*>(d.pop[p ^ 1]);
+    const Consts<T>& c = consts_of<T>(d);
+    const void* fin = d.pop[p];
+    char* fout = reinterpret_cast<char*>(d.pop[p ^ 1]);
     const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
     const int i = tx * TILE_X + (int)threadIdx.x;
-    const int j = ty;
-    const bool valid = i < d.nx;
+    const int j0 = ty * ROWS;
+    const int nx = d.nx, ny = d.ny;
+    const bool col_ok = i < nx;
+    const bool col_inner = i >= 1 && i <= nx - 2;
     const BodyDev& B = *d.body;
     const double X = B.q[p][0], Y = B.q[p][1];
     int bx0, bx1, by0, by1;
     body_tiles(d, B, X, Y, bx0, bx1, by0, by1);
     const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
 
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (valid) {
-        T g[NQ], out[NQ];
-        pull_node<S>(d, fin, i, j, g, true);
-        double chi = 0.0, usx = 0.0, usy = 0.0, rx = 0.0, ry = 0.0;
-        if (part && B.active) {
-            rx = (double)i - X;
-            ry = (double)j - Y;
-            chi = disc_chi(B, disc_d2(rx, ry));
-            const double om = B.v[p][2];
-            usx = B.v[p][0] - om * ry;
-            usy = B.v[p][1] + om * rx;
-        }
-        NodeOut<T> o;
-        collide<T>(d, g, (T)chi, (T)usx, (T)usy, out, o);
-        const long long base = (long long)j * d.pitch + i;
+    const char* P[NQ];
 #pragma unroll
-        for (int a = 0; a < NQ; ++a) Codec<S>::store(fout, a * d.ps + base, out[a], d.scale);
-        if (!(o.rho > T(0)) || !__builtin_isfinite(o.ux) || !__builtin_isfinite(o.uy))
-            atomicOr(d.flag, 1);
-        if (part) {
-            const double dFx = (double)o.dFx, dFy = (double)o.dFy;
-            const double rho = (double)o.rho, ux = (double)o.ux, uy = (double)o.uy;
-            acc[0] = dFx;
-            acc[1] = dFy;
-            acc[2] = rx * dFy - ry * dFx;
-            acc[3] = chi * rho * ux;
-            acc[4] = chi * rho * uy;
-            acc[5] = chi * rho * (rx * uy - ry * ux);
+    for (int a = 0; a < NQ; ++a) P[a] = plane<S>(d, fin, a);
+    const unsigned rowb = (unsigned)d.pitch * (unsigned)sizeof(S);
+    const float is = d.inv_scale;
+
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+
+    T g[NQ], gn[NQ];
+    if (col_ok && j0 < ny) {
+        if (col_inner && j0 >= 1 && j0 <= ny - 2)
+            pull_interior<S>(P, node_off<S>(d, i, j0), rowb, is, g);
+        else
+            pull_edge<S>(d, fin, i, j0, g, true);
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int j = j0 + r;
+        if (j >= ny) break;  // uniform over the workgroup
+        if (r + 1 < ROWS && j + 1 < ny && col_ok) {
+            if (col_inner && j + 1 <= ny - 2)
+                pull_interior<S>(P, node_off<S>(d, i, j + 1), rowb, is, gn);
+            else
+                pull_edge<S>(d, fin, i, j + 1, gn, true);
+        }
+        if (col_ok) {
+            double chi = 0.0, dsx = 0.0, dsy = 0.0, rx = 0.0, ry = 0.0;
+            if (part && B.active) {
+                rx = (double)i - X;
+                ry = (double)j - Y;
+                chi = disc_chi(B, disc_d2(rx, ry));
+                if (chi > 0.0) {
+                    const double om = B.v[p][2];
+                    dsx = (B.v[p][0] - om * ry) - d.u0x;
+                    dsy = (B.v[p][1] + om * rx) - d.u0y;
+                }
+            }
+            T out[NQ];
+            NodeOut<T> o;
+            collide<T>(c, g, (T)chi, (T)dsx, (T)dsy, out, o);
+            const unsigned off = node_off<S>(d, i, j);
+#pragma unroll
+            for (int a = 0; a < NQ; ++a)
+                Codec<S>::store(fout + (long long)a * d.ps * (long long)sizeof(S), off, out[a], d.scale);
+            if (!(o.rho > T(0)) || !__builtin_isfinite(o.ux) || !__builtin_isfinite(o.uy))
+                atomicOr(d.flag, 1);
+            if (part) {
+                const double dFx = (double)o.dFx, dFy = (double)o.dFy;
+                const double jx = (double)o.jgx + d.u0x, jy = (double)o.jgy + d.u0y;
+                const double px = jx + (double)o.Gx, py = jy + (double)o.Gy;
+                acc[0] += dFx;
+                acc[1] += dFy;
+                acc[2] += rx * dFy - ry * dFx;
+                acc[3] += chi * px;
+                acc[4] += chi * py;
+                acc[5] += chi * (rx * py - ry * px);
+                acc[6] += chi * jx;
+                acc[7] += chi * jy;
+                acc[8] += chi * (rx * jy - ry * jx);
+            }
+        }
+        if (r + 1 < ROWS) {
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) g[a] = gn[a];
         }
     }
     if (!part) return;  // uniform over the workgroup
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NRED; ++k) {
         const double s = wave_sum(acc[k]);
         if (lane == 0) red[wave][k] = s;
     }
@@ -535,10 +639,10 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tile, int p) {
     const int nb = nbx * (by1 - by0 + 1);
     if (threadIdx.x == 0) {
         const int slot = (ty - by0) * nbx + (tx - bx0);
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < NRED; ++k) {
             double s = red[0][k];
             for (int w = 1; w < NWAVE; ++w) s += red[w][k];
-            d.partials[(long long)slot * 6 + k] = s;
+            d.partials[(long long)slot * NRED + k] = s;
         }
         __threadfence();
         const unsigned prev = atomicAdd(d.counter, 1u);
@@ -547,19 +651,21 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tile, int p) {
     __syncthreads();
     if (!last) return;
     __threadfence();
-    double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double t[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) t[k] = 0.0;
     for (int s = threadIdx.x; s < nb; s += TILE_X)
-        for (int k = 0; k < 6; ++k) t[k] += d.partials[(long long)s * 6 + k];
+        for (int k = 0; k < NRED; ++k) t[k] += d.partials[(long long)s * NRED + k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NRED; ++k) {
         const double s = wave_sum(t[k]);
         if (lane == 0) red[wave][k] = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot[6];
-        for (int k = 0; k < 6; ++k) {
+        double tot[NRED];
+        for (int k = 0; k < NRED; ++k) {
             double s = red[0][k];
             for (int w = 1; w < NWAVE; ++w) s += red[w][k];
             tot[k] = s;

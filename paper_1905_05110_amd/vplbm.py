@@ -42,7 +42,8 @@ class Opts(C.Structure):
     _fields_ = [("bc", C.c_int * 4), ("u_wall", (C.c_double * 2) * 4), ("u_conv", C.c_double),
                 ("g_fluid", C.c_double * 2), ("rho0", C.c_double), ("u0", C.c_double * 2),
                 ("storage", C.c_int), ("fp16_scale_log2", C.c_int), ("history_cap", C.c_int),
-                ("hip_stream", C.c_void_p), ("pop_buffers", C.c_void_p * 2)]
+                ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("hip_stream", C.c_void_p),
+                ("pop_buffers", C.c_void_p * 2)]
 
 
 class Body(C.Structure):
@@ -123,6 +124,8 @@ def make_opts(spec, stream=None, buffers=None, history_cap=65536):
     o.storage = STORAGE[st] if isinstance(st, str) else int(st)
     o.fp16_scale_log2 = int(spec.get("fp16_scale_log2", 10))
     o.history_cap = int(history_cap)
+    o.offset_ref = {"initial": 0, "rest": 1}[spec.get("offset_ref", "initial")]
+    o.rows_per_tile = int(spec.get("rows_per_tile", 0))
     o.hip_stream = stream
     if buffers is not None:
         o.pop_buffers[0], o.pop_buffers[1] = buffers
