@@ -6,8 +6,10 @@ A step is one full fluid-structure step (pull-stream, penalization, MRT collisio
 FP64 force/torque reduction, RK4 body update) over the whole grid, all on the GPU.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second) of the timed
-region, the dominant kernel's achieved HBM bandwidth against the 8 TB/s peak, and the
-FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+region, the step kernel's achieved HBM bandwidth against the 8 TB/s peak, and the FP64
+CPU oracle timed on a bounded sample of the same workload on the host cores.  A step is
+exactly one kernel launch (replayed from captured HIP graphs), so the kernel's average
+duration is the timed region's event-measured time divided by the number of launches.
 """
 import argparse
 import json
@@ -27,14 +29,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--storage", default="fp32")
-    ap.add_argument("--graph-steps", type=int, default=0)
+    ap.add_argument("--storage", default="fp32", choices=sorted(BYTES_PER_NODE))
+    ap.add_argument("--graph-steps", type=int, default=64,
+                    help="steps per captured HIP graph in the timed region (0: eager launches)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per tile (0: autotune)")
+    ap.add_argument("--store", default="auto", choices=("auto", "plain", "nontemporal"))
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 256 MiB first (scale for HBM byte counters)")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON with measured HBM bytes per launch of the step kernel")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.txt"),
+                    help="measured HBM bytes per launch of the step kernel (from rocprofv3)")
     return ap.parse_args()
 
 
@@ -53,24 +59,50 @@ def cpu_baseline(wl, target_seconds):
     sim.step(n)
     dt = time.perf_counter() - t0
     nodes = wl["spec"]["nx"] * wl["spec"]["ny"]
-    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": orc.max_threads(),
+    return {"value": round(nodes * n / dt / 1e6, 2), "unit": "MLUPS", "cores": orc.max_threads(),
             "kind": "oracle",
-            "sample": "%d steps of the %dx%d grid (FP64, %.1f s)" % (n, wl["spec"]["nx"],
-                                                                     wl["spec"]["ny"], dt)}
+            "sample": "%d steps of the %dx%d grid (FP64 oracle, %.1f s)" % (
+                n, wl["spec"]["nx"], wl["spec"]["ny"], dt)}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1905_05110_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(path, storage, nx, ny, rows, nt):
+    """Measured HBM bytes per launch from the rocprofv3 counter summary, if one was
+    recorded for this configuration and for the kernel sources as they are now."""
+    if not path or not os.path.exists(path):
+        return None
+    want = "%s %d %d %s %d" % (storage, nx, ny, rows, int(bool(nt)))
+    src = kernel_source_hash()
+    for line in open(path):
+        f = line.split()
+        # traffic <storage> <nx> <ny> <rows> <nt> <source-hash> <bytes-per-launch>
+        if len(f) == 8 and f[0] == "traffic" and " ".join(f[1:6]) == want and f[6] == src:
+            return int(f[7])
+    return None
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md)", file=sys.stderr)
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1905_05110_amd import workloads as W
     from paper_1905_05110_amd import vplbm
 
     wl = W.free_viv(storage=args.storage)
-    spec, body = wl["spec"], wl["body"]
+    spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store)
+    body = wl["body"]
     nodes = spec["nx"] * spec["ny"]
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -80,29 +112,34 @@ def main():
         del src, dst
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        sim = vplbm.Sim(spec, body, torch_memory=True, history_cap=1 << 17,
-                        graph_steps=args.graph_steps)
+        sim = vplbm.Sim(spec, body, torch_memory=True, history_cap=1 << 17)
+        tuned = None
+        if not args.no_autotune and args.rows == 0 and args.store == "auto":
+            print("autotune", file=sys.stderr, flush=True)
+            tuned = sim.autotune(trial_steps=50)
+        rows, nt = (tuned[0], tuned[1]) if tuned else (None, None)
+        if args.graph_steps:
+            sim.set_graph_steps(args.graph_steps)
         print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
         sim.step(args.warmup)
         sim.sync()
         torch.cuda.synchronize()
-        # timed region: K steps, one kernel launch each, with a HIP event pair around
-        # every launch on the simulation's stream
+        # timed region: K full steps on the simulation's stream, bracketed by events
         print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
-        kernel_ms, region_ms = sim.step_timed(args.steps)
+        e0.record(stream)
+        sim.step(args.steps)
+        e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        region_ms = e0.elapsed_time(e1)
         sim.sync()
-        recs = sim.forces(cap=16)
     ms_per_step = region_ms / args.steps
     mlups = nodes * args.steps / (region_ms * 1e-3) / 1e6
-    avg_kernel_s = kernel_ms * 1e-3 / args.steps
+    avg_kernel_s = region_ms * 1e-3 / args.steps  # one step-kernel launch per step
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
     achieved = bytes_per_launch / avg_kernel_s / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
     out = {
         "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step)",
         "value": round(mlups, 1),
@@ -114,14 +151,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "fp32" else args.storage,
-        "data": "synthetic (seeded lattice state, no dataset)",
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f32 (fp16 storage)",
+                  "bf16": "f32 (bf16 storage)"}[args.storage],
+        "data": "synthetic (lattice flow from a uniform inflow state; no dataset)",
         "config": {"workload": "free_viv_2048x1024", "nx": spec["nx"], "ny": spec["ny"],
                    "storage": args.storage, "body": "disc D=40, free in y, mass ratio 10, U_r 5",
-                   "Re": 150, "graph_steps": args.graph_steps},
+                   "Re": 150, "graph_steps": args.graph_steps,
+                   "rows_per_tile": rows if rows else args.rows,
+                   "nontemporal_stores": bool(nt) if nt is not None else args.store},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step<%s>" % args.storage,
+                     "traffic": traffic_for(args.traffic, args.storage, spec["nx"], spec["ny"],
+                                            rows, nt),
+                     "kernel": "k_step<%s>" % args.storage,
                      "avg_kernel_us": round(avg_kernel_s * 1e6, 3),
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "wall_s": round(wall, 3),

@@ -68,6 +68,11 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * weights w_a = f_eq(1, 0). */
 enum { LBM_REF_INITIAL = 0, LBM_REF_REST = 1 };
 
+/* Store instructions for the populations: PLAIN keeps them in the caches (a grid whose
+ * two buffers fit the 256 MB Infinity Cache then runs from it); NONTEMPORAL streams
+ * them past the caches; AUTO picks NONTEMPORAL above 1 GiB of buffers. */
+enum { LBM_STORE_AUTO = 0, LBM_STORE_PLAIN = 1, LBM_STORE_NONTEMPORAL = 2 };
+
 /* Boundary rule of one domain side (Sec. 3.1 for the channel set-up).
  *   PERIODIC  wrap around (both opposite sides must be periodic);
  *   WALL      no-slip half-way bounce-back;
@@ -107,8 +112,12 @@ typedef struct {
     int fp16_scale_log2;   /* k of the FP16 offset scale 2^k, 0..14 (default 10) */
     int history_cap;       /* force records kept on the device between drains (default 65536) */
     int offset_ref;        /* LBM_REF_INITIAL (default) or LBM_REF_REST */
-    int rows_per_tile;     /* grid rows per 256-column tile (nodes per lane): 1, 2, 4, 8;
-                              0 = default.  Results do not depend on it. */
+    int rows_per_tile;     /* grid rows per 256-column tile (nodes per lane): 1, 2, 4;
+                              0 = default.  Each setting is deterministic; results of
+                              different settings agree to rounding (kernel variants may
+                              contract multiply-adds differently; FP64 force sums follow
+                              the tile order). */
+    int store_mode;        /* LBM_STORE_AUTO (default), _PLAIN or _NONTEMPORAL */
     void* hip_stream;      /* hipStream_t to run on; NULL: the library creates one */
     void* pop_buffers[2];  /* optional caller-owned device buffers of lbm_pop_bytes() each */
 } lbm_opts;
@@ -194,9 +203,21 @@ int lbm_get_body_state(lbm_sim* sim, double* q, double* v);
 /* Number of steps enqueued since creation. */
 int64_t lbm_step_index(const lbm_sim* sim);
 
-/* Enqueues n steps with a HIP event pair around every kernel launch, synchronises and
- * returns the summed kernel time (ms) and the wall time of the whole region (ms). */
+/* Enqueues n steps with a HIP event pair around every launch of the step kernel (the
+ * grid-wide pull/collide kernel; the one-workgroup finalisation that follows it is
+ * outside the pair), synchronises and returns the summed step-kernel time (ms) and the
+ * time of the whole region (ms). */
 int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms);
+
+/* Chooses the launch configuration of the step kernel (rows per tile 1/2/4, plain or
+ * nontemporal stores) by timing trial_steps steps of each candidate on a scratch
+ * simulation of the same grid and storage, and applies it to sim (whose state is not
+ * touched).  cache_path (may be NULL) names a JSON-lines file: a configuration found
+ * there for this device, storage and grid is applied without timing, and a newly
+ * timed one is appended.  Outputs (each may be NULL): the chosen rows, nt flag, and
+ * the measured time per step in microseconds (-1 when taken from the cache). */
+int lbm_autotune(lbm_sim* sim, int trial_steps, const char* cache_path, int* rows_out,
+                 int* nt_out, double* us_out);
 
 /* Serialises the full state (populations, outflow memory, body, step index) into a
  * host buffer; with buf NULL only *size_out is set.  lbm_load restores a state saved

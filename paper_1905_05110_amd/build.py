@@ -1,47 +1,72 @@
 """Compile the HIP library ``libvplbm.so`` for gfx950 (MI355X).
 
-``python -m paper_1905_05110_amd.build`` runs hipcc on ``csrc/vplbm.hip``.  The
-library is written in-tree next to this file.  Packed FP32 instructions are turned
-off for device code (``-packed-fp32-ops``); hipcc's host pass warns that it does not
-know the feature, which is harmless.
+``python -m paper_1905_05110_amd.build`` compiles the host runtime (``csrc/vplbm.hip``)
+and one kernel translation unit per population storage (``csrc/kern_*.hip``) in
+parallel with hipcc, then links them into ``libvplbm.so`` next to this file.  Packed
+FP32 instructions are turned off for device code (``-packed-fp32-ops``); hipcc's host
+pass warns that it does not know the feature, which is harmless.
 """
+import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "vplbm.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "vplbm_device.hpp"), os.path.join(ROOT, "include", "vplbm.h")]
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvplbm.so")
+OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("VPLBM_OFFLOAD_ARCH", "gfx950")
 
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
+         "-Wno-unused-command-line-argument", "-Wno-unused-result",
+         "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def deps():
+    return sources() + sorted(glob.glob(os.path.join(CSRC, "*.hpp"))) + \
+        [os.path.join(ROOT, "include", "vplbm.h")]
 
 
 def stale() -> bool:
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(d) > t for d in DEPS)
+    return any(os.path.getmtime(d) > t for d in deps())
+
+
+def _compile(src, verbose):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = ["hipcc"] + FLAGS + ["-c", "-o", obj, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s%s" % (src, r.stdout, r.stderr))
+    return obj
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and not stale():
         return LIB
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), sources()))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + FLAGS + ["-o", tmp, SRC]
-    if verbose:
-        print(" ".join(cmd))
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for %s" % SRC)
+        raise RuntimeError("link failed:\n%s%s" % (r.stdout, r.stderr))
     os.replace(tmp, LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(force=True, verbose=True))
+    print(build(force=True, verbose="-v" in sys.argv))

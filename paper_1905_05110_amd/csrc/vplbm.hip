@@ -15,86 +15,15 @@
 #include <vector>
 
 #include "vplbm.h"
-#include "vplbm_device.hpp"
+#include "vplbm_kernels.hpp"
 
 using namespace vplbm;
 
-// ---------------------------------------------------------------------------------
-// kernels
-// ---------------------------------------------------------------------------------
-template <class S, int ROWS>
-__global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ dp, int p) {
-    const SimDesc& d = *dp;
-    step_tile<S, ROWS>(d, xcd_tile((int)blockIdx.x, (int)gridDim.x), p);
+namespace vplbm {
+__global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p) {
+    finalize_step(*dp, p);
 }
-
-// Fill one buffer's planes with constant offsets (initial equilibrium).
-template <class S>
-__global__ void k_fill(SimDesc d, double g0, double g1, double g2, double g3, double g4, double g5,
-                       double g6, double g7, double g8, int buf) {
-    using T = typename Codec<S>::T;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= d.nx) return;
-    const double g[NQ] = {g0, g1, g2, g3, g4, g5, g6, g7, g8};
-    const unsigned off = node_off<S>(d, i, j);
-    for (int a = 0; a < NQ; ++a)
-        Codec<S>::store(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)g[a], d.scale);
-}
-
-// Host FP64 populations f [9][ny][nx] <-> stored offsets.
-template <class S>
-__global__ void k_set_pop(SimDesc d, const double* __restrict__ f, int buf) {
-    using T = typename Codec<S>::T;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= d.nx) return;
-    const long long plane_n = (long long)d.nx * d.ny;
-    const unsigned off = node_off<S>(d, i, j);
-    for (int a = 0; a < NQ; ++a) {
-        const double v = f[a * plane_n + (long long)j * d.nx + i] - d.fref[a];
-        Codec<S>::store(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)v, d.scale);
-    }
-}
-
-template <class S>
-__global__ void k_get_pop(SimDesc d, double* __restrict__ f, int buf) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= d.nx) return;
-    const long long plane_n = (long long)d.nx * d.ny;
-    const unsigned off = node_off<S>(d, i, j);
-    for (int a = 0; a < NQ; ++a)
-        f[a * plane_n + (long long)j * d.nx + i] =
-            (double)Codec<S>::load(plane<S>(d, d.pop[buf], a), off, d.inv_scale) + d.fref[a];
-}
-
-// Density and penalized velocity of the current state, body at its current pose.
-template <class S>
-__global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
-    using T = typename Codec<S>::T;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= d.nx) return;
-    T g[NQ];
-    pull_edge<S>(d, d.pop[p], i, j, g, false);
-    const BodyDev& B = *d.body;
-    double chi = 0.0, dsx = 0.0, dsy = 0.0;
-    if (B.active) {
-        const double rx = (double)i - B.q[p][0], ry = (double)j - B.q[p][1];
-        chi = disc_chi(B, disc_d2(rx, ry));
-        if (chi > 0.0) {
-            dsx = (B.v[p][0] - B.v[p][2] * ry) - d.u0x;
-            dsy = (B.v[p][1] + B.v[p][2] * rx) - d.u0y;
-        }
-    }
-    NodeOut<T> o;
-    macros<T>(consts_of<T>(d), g, (T)chi, (T)dsx, (T)dsy, o);
-    const long long plane_n = (long long)d.nx * d.ny, o_ = (long long)j * d.nx + i;
-    out[o_] = (double)o.rho;
-    out[plane_n + o_] = d.u0x + (double)o.dux;
-    out[2 * plane_n + o_] = d.u0y + (double)o.duy;
-}
+}  // namespace vplbm
 
 // ---------------------------------------------------------------------------------
 // host runtime
@@ -129,7 +58,6 @@ struct lbm_sim {
     void* outlet = nullptr;
     BodyDev* body_d = nullptr;
     double* partials = nullptr;
-    unsigned* counter = nullptr;
     Record* hist = nullptr;
     int* flag = nullptr;
     double* staging = nullptr;  // FP64 [9][ny][nx] for set/get/fields
@@ -144,9 +72,12 @@ struct lbm_sim {
     lbm_rates rates{};
     double eta = 0.0;
     BodyDev body_h{};
+    lbm_body body_desc{};  // last body set (used by the autotuner)
+    bool has_body = false;
     std::string err;
     int graph_steps = 0;
-    int rows = 4;  // rows of a tile (nodes per lane)
+    int rows = 1;   // rows of a tile (nodes per lane)
+    bool nt = false;  // nontemporal population stores
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -165,7 +96,6 @@ static int fail(lbm_sim* s, int code, const std::string& msg) {
     return code;
 }
 
-static dim3 grid_rows(const lbm_sim* s) { return dim3((s->nx + 255) / 256, s->ny); }
 
 template <class F>
 static int dispatch(int storage, F&& f) {
@@ -202,26 +132,28 @@ static void drop_graph(lbm_sim* s) {
     s->graph = nullptr;
 }
 
-template <class S>
-static void launch_rows(lbm_sim* s, int ntiles, int p) {
-    switch (s->rows) {
-        case 1: hipLaunchKernelGGL((k_step<S, 1>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
-        case 2: hipLaunchKernelGGL((k_step<S, 2>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
-        case 8: hipLaunchKernelGGL((k_step<S, 8>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
-        default: hipLaunchKernelGGL((k_step<S, 4>), dim3(ntiles), dim3(TILE_X), 0, s->stream, s->desc_d, p); break;
-    }
-}
-
-static int launch_step(lbm_sim* s) {
+// One fluid-structure step: one kernel launch (ev0/ev1, optional, bracket it).
+static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     const int p = (int)(s->host_step & 1);
-    const int ntiles = s->desc.tiles_x * s->desc.tiles_y;
+    const dim3 grid(s->desc.tiles_x, s->desc.tiles_y);
+    if (ev0) HIP_TRY(s, hipEventRecord(ev0, s->stream));
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        launch_rows<S>(s, ntiles, p);
+        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, p, s->stream);
         return LBM_OK;
     });
+    if (ev1) HIP_TRY(s, hipEventRecord(ev1, s->stream));
     HIP_TRY(s, hipGetLastError());
     s->host_step += 1;
+    return LBM_OK;
+}
+
+// Makes the body state of the next step final and writes the last step's record
+// (the step kernels defer that work to their successor).  Enqueued on the stream.
+static int flush_state(lbm_sim* s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TILE_X), 0, s->stream, s->desc_d,
+                       (int)(s->host_step & 1));
+    HIP_TRY(s, hipGetLastError());
     return LBM_OK;
 }
 
@@ -267,8 +199,10 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
         return m = "fp16_scale_log2 must lie in 0..14", LBM_ERR_ARG;
     if (o.history_cap < 1) return m = "history_cap must be >= 1", LBM_ERR_ARG;
     if (o.rows_per_tile != 0 && o.rows_per_tile != 1 && o.rows_per_tile != 2 &&
-        o.rows_per_tile != 4 && o.rows_per_tile != 8)
-        return m = "rows_per_tile must be 0, 1, 2, 4 or 8", LBM_ERR_ARG;
+        o.rows_per_tile != 4)
+        return m = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
+    if (o.store_mode < LBM_STORE_AUTO || o.store_mode > LBM_STORE_NONTEMPORAL)
+        return m = "unknown store mode", LBM_ERR_ARG;
     if (o.offset_ref != LBM_REF_INITIAL && o.offset_ref != LBM_REF_REST)
         return m = "unknown offset reference", LBM_ERR_ARG;
     if (!(o.rho0 > 0.0)) return m = "rho0 must be > 0", LBM_ERR_ARG;
@@ -283,7 +217,7 @@ static void free_sim(lbm_sim* s) {
         if (s->pop[0]) hipFree(s->pop[0]);
         if (s->pop[1]) hipFree(s->pop[1]);
     }
-    void* bufs[] = {s->outlet, s->body_d, s->partials, s->counter, s->hist, s->flag, s->staging,
+    void* bufs[] = {s->outlet, s->body_d, s->partials, s->hist, s->flag, s->staging,
                     s->desc_d};
     for (void* b : bufs)
         if (b) hipFree(b);
@@ -344,14 +278,19 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
         CREATE_TRY(hipMalloc(&s->pop[1], s->pop_bytes));
     }
     const size_t tsz = o.storage == LBM_FP64 ? 8 : 4;
-    s->rows = o.rows_per_tile ? o.rows_per_tile : 4;
+    // Launch configuration defaults (lbm_autotune refines them): two rows per lane for
+    // grids up to 2.5 M nodes with FP32 arithmetic, one otherwise; nontemporal stores once
+    // the two population buffers exceed 1 GiB (far beyond the 256 MB Infinity Cache).
+    s->rows = o.rows_per_tile ? o.rows_per_tile
+                              : ((o.storage != LBM_FP64 && (long long)nx * ny <= 2500000) ? 2 : 1);
+    s->nt = o.store_mode == LBM_STORE_NONTEMPORAL ||
+            (o.store_mode == LBM_STORE_AUTO && 2 * s->pop_bytes > (size_t(1) << 30));
     const int tiles_x = (nx + TILE_X - 1) / TILE_X;
     const int tiles_y = (ny + s->rows - 1) / s->rows;
-    const int ntiles = tiles_x * tiles_y;
+    const int ntiles = tiles_x * ny;  // enough slots for any rows per tile
     CREATE_TRY(hipMalloc(&s->outlet, 3 * (size_t)ny * tsz));
     CREATE_TRY(hipMalloc((void**)&s->body_d, sizeof(BodyDev)));
-    CREATE_TRY(hipMalloc((void**)&s->partials, (size_t)ntiles * NRED * sizeof(double)));
-    CREATE_TRY(hipMalloc((void**)&s->counter, 64));
+    CREATE_TRY(hipMalloc((void**)&s->partials, 2 * (size_t)ntiles * NRED * sizeof(double)));
     CREATE_TRY(hipMalloc((void**)&s->hist, (size_t)s->hist_cap * sizeof(Record)));
     CREATE_TRY(hipMalloc((void**)&s->flag, 64));
     CREATE_TRY(hipMalloc((void**)&s->staging, (size_t)NQ * nx * ny * sizeof(double)));
@@ -363,7 +302,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.outlet = s->outlet;
     d.body = s->body_d;
     d.partials = s->partials;
-    d.counter = s->counter;
+    d.part_stride = (long long)ntiles * NRED;
     d.hist = s->hist;
     d.flag = s->flag;
     d.ps = plane_stride(nx, ny);
@@ -424,16 +363,13 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     // initial state: equilibrium at (rho0, u0) in both buffers, outflow memory alike
     CREATE_TRY(hipMemsetAsync(s->pop[0], 0, s->pop_bytes, s->stream));
     CREATE_TRY(hipMemsetAsync(s->pop[1], 0, s->pop_bytes, s->stream));
-    CREATE_TRY(hipMemsetAsync(s->counter, 0, 64, s->stream));
     CREATE_TRY(hipMemsetAsync(s->flag, 0, 64, s->stream));
     double g[NQ];
     equilibrium(o.rho0, o.u0[0], o.u0[1], g);
     for (int a = 0; a < NQ; ++a) g[a] -= d.fref[a];
     dispatch(o.storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        for (int b = 0; b < 2; ++b)
-            hipLaunchKernelGGL(k_fill<S>, grid_rows(s), dim3(256), 0, s->stream, d, g[0], g[1],
-                               g[2], g[3], g[4], g[5], g[6], g[7], g[8], b);
+        for (int b = 0; b < 2; ++b) Launch<S>::fill(d, g, b, s->stream);
         return 0;
     });
     CREATE_TRY(hipGetLastError());
@@ -453,7 +389,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     }
     std::memset(&s->body_h, 0, sizeof(BodyDev));
     s->body_h.active = 0;
-    s->body_h.step = 0;
+    s->body_h.st[0].fresh = 1;  // step 0 takes this (absent-body) state as is
     CREATE_TRY(hipMemcpyAsync(s->body_d, &s->body_h, sizeof(BodyDev), hipMemcpyHostToDevice,
                               s->stream));
     CREATE_TRY(hipMemcpyAsync(s->desc_d, &s->desc, sizeof(SimDesc), hipMemcpyHostToDevice,
@@ -472,10 +408,13 @@ int lbm_destroy(lbm_sim* s) {
 }
 
 static int sync_check(lbm_sim* s) {
+    int rc = flush_state(s);
+    if (rc) return rc;
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     int flag = 0;
     HIP_TRY(s, hipMemcpy(&flag, s->flag, sizeof(int), hipMemcpyDeviceToHost));
-    if (flag) return fail(s, LBM_ERR_UNSTABLE, "non-positive or non-finite density/velocity met");
+    if (flag & 1) return fail(s, LBM_ERR_UNSTABLE, "non-positive or non-finite density/velocity met");
+    if (flag & 2) return fail(s, LBM_ERR_UNSTABLE, "body moved two or more nodes in one step");
     return LBM_OK;
 }
 
@@ -497,7 +436,8 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     const double vals[] = {b->x, b->y, b->theta, b->vx, b->vy, b->omega};
     for (double x : vals)
         if (!std::isfinite(x)) return fail(s, LBM_ERR_ARG, "non-finite pose or velocity");
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    int rc = sync_check(s);  // finish pending work and its record first
+    if (rc && rc != LBM_ERR_UNSTABLE) return rc;
     BodyDev B;
     std::memset(&B, 0, sizeof(B));
     B.active = 1;
@@ -526,25 +466,37 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
         q[1] = b->imp_y0;  // sin(0) = 0
         v[1] = 6.283185307179586476925286766559 * b->imp_freq * b->imp_amp;
     }
+    BodyState& st = B.st[p];
     for (int k = 0; k < 3; ++k) {
-        B.q[p][k] = B.q[p ^ 1][k] = q[k];
-        B.v[p][k] = B.v[p ^ 1][k] = v[k];
+        st.q[k] = q[k];
+        st.v[k] = v[k];
     }
-    B.t_body = 0;
-    B.step = s->host_step;
-    B.pin_valid = 0;
+    st.t_body = 0;
+    st.step = s->host_step;
+    st.pin_valid = 0;
+    st.fresh = 1;
+    body_tiles(s->nx, s->ny, s->rows, B, q[0], q[1], st.boxM);
+    for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
     s->body_h = B;
+    s->body_desc = *b;
+    s->has_body = true;
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     return LBM_OK;
 }
 
 int lbm_clear_body(lbm_sim* s) {
     if (!s) return LBM_ERR_ARG;
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    int rc = sync_check(s);
+    if (rc && rc != LBM_ERR_UNSTABLE) return rc;
     BodyDev B;
     HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
+    const int p = (int)(s->host_step & 1);
     B.active = 0;
-    B.pin_valid = 0;
+    BodyState& st = B.st[p];
+    st.pin_valid = 0;
+    st.fresh = 1;
+    for (int k = 0; k < 4; ++k) st.boxM[k] = st.part_box[k] = 0;
+    s->has_body = false;
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     return LBM_OK;
 }
@@ -610,11 +562,7 @@ int lbm_step_timed(lbm_sim* s, int64_t n, double* kernel_ms, double* region_ms) 
     for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
     HIP_TRY(s, hipEventRecord(ev[0], s->stream));
     int rc = LBM_OK;
-    for (int64_t k = 0; k < n && rc == LBM_OK; ++k) {
-        hipEventRecord(ev[2 + 2 * k], s->stream);
-        rc = launch_step(s);
-        hipEventRecord(ev[3 + 2 * k], s->stream);
-    }
+    for (int64_t k = 0; k < n && rc == LBM_OK; ++k) rc = launch_step(s, ev[2 + 2 * k], ev[3 + 2 * k]);
     HIP_TRY(s, hipEventRecord(ev[1], s->stream));
     HIP_TRY(s, hipEventSynchronize(ev[1]));
     double ksum = 0.0;
@@ -635,11 +583,9 @@ int64_t lbm_step_index(const lbm_sim* s) { return s ? s->host_step : -1; }
 
 int lbm_forces(lbm_sim* s, lbm_force_rec* out, int64_t cap, int64_t* n_out) {
     if (!s || (!out && cap > 0) || cap < 0) return fail(s, LBM_ERR_ARG, "bad argument");
-    int rc = sync_check(s);
+    int rc = sync_check(s);  // flushes: records exist for every enqueued step
     if (n_out) *n_out = 0;
-    BodyDev B;
-    HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
-    const int64_t written = B.step;  // records exist for steps < B.step
+    const int64_t written = s->host_step;
     if (s->drained < written - s->hist_cap) s->drained = written - s->hist_cap;
     int64_t n = std::min<int64_t>(written - s->drained, cap);
     static_assert(sizeof(Record) == sizeof(lbm_force_rec), "record layout");
@@ -658,10 +604,11 @@ int lbm_forces(lbm_sim* s, lbm_force_rec* out, int64_t cap, int64_t* n_out) {
 int lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy) {
     if (!s || !rho || !ux || !uy) return fail(s, LBM_ERR_ARG, "NULL argument");
     const int p = (int)(s->host_step & 1);
+    int frc = flush_state(s);
+    if (frc) return frc;
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_fields<S>, grid_rows(s), dim3(256), 0, s->stream, s->desc,
-                           s->staging, p);
+        Launch<S>::fields(s->desc, s->staging, p, s->stream);
         return 0;
     });
     HIP_TRY(s, hipGetLastError());
@@ -681,8 +628,7 @@ int lbm_set_populations(lbm_sim* s, const double* f) {
     const int p = (int)(s->host_step & 1);
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_set_pop<S>, grid_rows(s), dim3(256), 0, s->stream, s->desc,
-                           s->staging, p);
+        Launch<S>::set_pop(s->desc, s->staging, p, s->stream);
         return 0;
     });
     HIP_TRY(s, hipGetLastError());
@@ -695,8 +641,7 @@ int lbm_get_populations(lbm_sim* s, double* f) {
     const int p = (int)(s->host_step & 1);
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        hipLaunchKernelGGL(k_get_pop<S>, grid_rows(s), dim3(256), 0, s->stream, s->desc,
-                           s->staging, p);
+        Launch<S>::get_pop(s->desc, s->staging, p, s->stream);
         return 0;
     });
     HIP_TRY(s, hipGetLastError());
@@ -707,14 +652,129 @@ int lbm_get_populations(lbm_sim* s, double* f) {
 
 int lbm_get_body_state(lbm_sim* s, double* q, double* v) {
     if (!s || !q || !v) return fail(s, LBM_ERR_ARG, "NULL argument");
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    int rc = sync_check(s);
     BodyDev B;
     HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
     const int p = (int)(s->host_step & 1);
     for (int k = 0; k < 3; ++k) {
-        q[k] = B.q[p][k];
-        v[k] = B.v[p][k];
+        q[k] = B.st[p].q[k];
+        v[k] = B.st[p].v[k];
     }
+    return rc;
+}
+
+// ---- launch configuration and its autotuning ---------------------------------------
+static int apply_launch_config(lbm_sim* s, int rows, bool nt) {
+    int rc0 = sync_check(s);  // the next step's state is then fresh
+    if (rc0 && rc0 != LBM_ERR_UNSTABLE) return rc0;
+    s->rows = rows;
+    s->nt = nt;
+    s->desc.rows = rows;
+    s->desc.tiles_y = (s->ny + rows - 1) / rows;
+    BodyDev B;
+    HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
+    BodyState& st = B.st[s->host_step & 1];
+    body_tiles(s->nx, s->ny, rows, B, st.q[0], st.q[1], st.boxM);
+    for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
+    HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
+    int rc = upload_desc(s);
+    if (rc) return rc;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    return LBM_OK;
+}
+
+static std::string tune_key(const lbm_sim* s) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "%s/s%d/%dx%d", arch.c_str(), s->storage, s->nx, s->ny);
+    return buf;
+}
+
+// Cache lines: {"key": "<arch>/s<storage>/<nx>x<ny>", "rows": r, "nt": 0|1, "us": t}
+static bool tune_lookup(const char* path, const std::string& key, int& rows, int& nt) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[256];
+        int r = 0, n = 0;
+        double us = 0;
+        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"rows\": %d, \"nt\": %d, \"us\": %lf", k, &r,
+                        &n, &us) == 4 &&
+            key == k && (r == 1 || r == 2 || r == 4) && (n == 0 || n == 1)) {
+            rows = r;
+            nt = n;
+            found = true;  // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_out, int* nt_out,
+                 double* us_out) {
+    if (!s || trial_steps < 1) return fail(s, LBM_ERR_ARG, "bad argument");
+    const std::string key = tune_key(s);
+    int rows = 0, nt = 0;
+    double best = -1.0;
+    if (!(cache_path && tune_lookup(cache_path, key, rows, nt))) {
+        const int cand_rows[3] = {1, 2, 4};
+        for (int ci = 0; ci < 6; ++ci) {
+            lbm_opts o = s->opts;
+            o.hip_stream = nullptr;
+            o.pop_buffers[0] = o.pop_buffers[1] = nullptr;
+            o.history_cap = 64;
+            o.rows_per_tile = cand_rows[ci / 2];
+            o.store_mode = (ci & 1) ? LBM_STORE_NONTEMPORAL : LBM_STORE_PLAIN;
+            lbm_sim* t = nullptr;
+            int rc = lbm_create(s->nx, s->ny, s->rates, s->eta, &o, &t);
+            if (rc) return fail(s, rc, std::string("autotune: ") + lbm_last_error(nullptr));
+            if (s->has_body && lbm_set_body(t, &s->body_desc) != LBM_OK) {
+                lbm_destroy(t);
+                return fail(s, LBM_ERR_HIP, "autotune: body");
+            }
+            hipEvent_t e0, e1;
+            float ms = 0.f;
+            bool ok = lbm_step(t, 3) == LBM_OK && hipEventCreate(&e0) == hipSuccess &&
+                      hipEventCreate(&e1) == hipSuccess &&
+                      hipEventRecord(e0, t->stream) == hipSuccess &&
+                      lbm_step(t, trial_steps) == LBM_OK &&
+                      hipEventRecord(e1, t->stream) == hipSuccess &&
+                      hipEventSynchronize(e1) == hipSuccess &&
+                      hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            lbm_destroy(t);
+            if (!ok) return fail(s, LBM_ERR_HIP, "autotune: timing run failed");
+            const double us = 1e3 * ms / trial_steps;
+            if (best < 0.0 || us < best) {
+                best = us;
+                rows = cand_rows[ci / 2];
+                nt = ci & 1;
+            }
+        }
+        if (cache_path) {
+            FILE* f = std::fopen(cache_path, "a");
+            if (f) {
+                std::fprintf(f, "{\"key\": \"%s\", \"rows\": %d, \"nt\": %d, \"us\": %.3f}\n",
+                             key.c_str(), rows, nt, best);
+                std::fclose(f);
+            }
+        }
+    }
+    int rc = apply_launch_config(s, rows, nt != 0);
+    if (rc) return rc;
+    if (rows_out) *rows_out = rows;
+    if (nt_out) *nt_out = nt;
+    if (us_out) *us_out = best;
     return LBM_OK;
 }
 

@@ -62,6 +62,18 @@ __host__ __device__ __forceinline__ int dir_flip_y(int a) {
 }
 
 // ---- device-resident state --------------------------------------------------------
+// Tile ranges are (tx0, tx1, ty0, ty1), inclusive.
+struct BodyState {
+    double q[3], v[3];   // pose (X, Y, theta) and velocities used by the step
+    double pin_prev[3];  // internal momentum P_in of the previous step
+    long long t_body;    // steps since the body was set (phase of the imposed motion)
+    long long step;      // index of the step that uses this state
+    int pin_valid;       // 0 on the first step after the body is set
+    int fresh;           // 1: written by the host or a flush; the step takes it as is
+    int boxM[4];         // tiles within the support of this pose plus a 3-node margin
+    int part_box[4];     // tiles that took part in this state's step (its partial slots)
+};
+
 struct BodyDev {
     // constants of the disc and its motion law
     int active, mode;
@@ -72,12 +84,10 @@ struct BodyDev {
     double mass, inertia;
     double k[3], c[3], q0[3], fext[3];
     double amp, freq, y0;
-    // state, double-buffered by step parity: step n reads [n & 1], writes [(n + 1) & 1]
-    double q[2][3], v[2][3];
-    long long t_body;  // steps since the body was set
-    long long step;    // index of the next step
-    double pin_prev[3];
-    int pin_valid, pad1;
+    // State of step n in st[n & 1].  Step n's kernel derives it from st[(n - 1) & 1] and
+    // the partial sums of step n - 1 (every tile that needs it, identically) unless the
+    // host or a flush already wrote it ("fresh").
+    BodyState st[2];
 };
 
 struct Record {  // same layout as lbm_force_rec
@@ -100,8 +110,8 @@ struct SimDesc {
     void* pop[2];        // two population buffers, 9 planes of ps elements each
     void* outlet;        // 3 x ny offsets (directions 3, 6, 7) of the outflow memory
     BodyDev* body;
-    double* partials;    // NRED FP64 sums per participating tile
-    unsigned* counter;   // arrival counter of the participating tiles
+    double* partials;    // NRED FP64 sums per participating tile, two parities
+    long long part_stride;  // doubles per parity in partials
     Record* hist;        // ring of per-step records
     int* flag;           // set to 1 when an unstable node is met
     long long ps;        // plane stride (elements)
@@ -139,8 +149,10 @@ struct Codec<double> {
     static __device__ __forceinline__ T load(const char* base, unsigned off, float) {
         return *reinterpret_cast<const double*>(base + off);
     }
+    template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float) {
-        __builtin_nontemporal_store(v, reinterpret_cast<double*>(base + off));
+        double* q = reinterpret_cast<double*>(base + off);
+        if (NT) __builtin_nontemporal_store(v, q); else *q = v;
     }
 };
 
@@ -150,8 +162,10 @@ struct Codec<float> {
     static __device__ __forceinline__ T load(const char* base, unsigned off, float) {
         return *reinterpret_cast<const float*>(base + off);
     }
+    template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float) {
-        __builtin_nontemporal_store(v, reinterpret_cast<float*>(base + off));
+        float* q = reinterpret_cast<float*>(base + off);
+        if (NT) __builtin_nontemporal_store(v, q); else *q = v;
     }
 };
 
@@ -162,8 +176,11 @@ struct Codec<_Float16> {
     static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
         return (float)*reinterpret_cast<const _Float16*>(base + off) * inv_scale;
     }
+    template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
-        __builtin_nontemporal_store((_Float16)(v * scale), reinterpret_cast<_Float16*>(base + off));
+        _Float16* q = reinterpret_cast<_Float16*>(base + off);
+        const _Float16 h = (_Float16)(v * scale);
+        if (NT) __builtin_nontemporal_store(h, q); else *q = h;
     }
 };
 
@@ -181,8 +198,11 @@ struct Codec<bf16s> {
         const uint16_t b = *reinterpret_cast<const uint16_t*>(base + off);
         return __builtin_bit_cast(float, (uint32_t)b << 16) * inv_scale;
     }
+    template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
-        __builtin_nontemporal_store(f32_to_bf16_rne(v * scale), reinterpret_cast<uint16_t*>(base + off));
+        uint16_t* q = reinterpret_cast<uint16_t*>(base + off);
+        const uint16_t b = f32_to_bf16_rne(v * scale);
+        if (NT) __builtin_nontemporal_store(b, q); else *q = b;
     }
 };
 
@@ -310,19 +330,23 @@ __device__ __forceinline__ double disc_chi(const BodyDev& B, double d2) {
 // Tile range (inclusive) of the tiles that meet the support of the body; all its
 // nodes with chi > 0 lie inside.  An absent or out-of-domain body maps to tile (0, 0)
 // alone, so that exactly one workgroup finalises every step.
-__device__ __forceinline__ void body_tiles(const SimDesc& d, const BodyDev& B, double X, double Y,
-                                           int& tx0, int& tx1, int& ty0, int& ty1) {
-    tx0 = tx1 = ty0 = ty1 = 0;
+// Evaluated once per step (by the workgroup that advances the body, and on the host
+// when the body is set) and stored per parity in BodyDev::box.
+// margin: nodes added around the support (1 for the exact box, 3 for participation).
+constexpr double BOX_MARGIN = 3.0;
+__host__ __device__ inline void body_tiles(int nx, int ny, int rows, const BodyDev& B, double X,
+                                           double Y, int box[4], double margin = BOX_MARGIN) {
+    box[0] = box[1] = box[2] = box[3] = 0;
     if (!B.active) return;
-    const double xl = fmax(floor(X - B.reach) - 1.0, 0.0);
-    const double xh = fmin(ceil(X + B.reach) + 1.0, (double)(d.nx - 1));
-    const double yl = fmax(floor(Y - B.reach) - 1.0, 0.0);
-    const double yh = fmin(ceil(Y + B.reach) + 1.0, (double)(d.ny - 1));
+    const double xl = fmax(floor(X - B.reach) - margin, 0.0);
+    const double xh = fmin(ceil(X + B.reach) + margin, (double)(nx - 1));
+    const double yl = fmax(floor(Y - B.reach) - margin, 0.0);
+    const double yh = fmin(ceil(Y + B.reach) + margin, (double)(ny - 1));
     if (!(xl <= xh) || !(yl <= yh)) return;
-    tx0 = (int)xl / TILE_X;
-    tx1 = (int)xh / TILE_X;
-    ty0 = (int)yl / d.rows;
-    ty1 = (int)yh / d.rows;
+    box[0] = (int)xl / TILE_X;
+    box[1] = (int)xh / TILE_X;
+    box[2] = (int)yl / rows;
+    box[3] = (int)yh / rows;
 }
 
 // ---- macroscopic quantities, penalized velocity and MRT collision ------------------
@@ -347,7 +371,7 @@ __device__ __forceinline__ float recip<float>(float x) {
 // ds = u_s - u_ref:  r = (jg - drho u_ref + rho g/2 - rho ds) / (rho (1 + lam/2)),
 // u - u_ref = ds + r.  Where chi = 0 the result does not depend on u_s, and ds = 0
 // is passed so that no term cancels against u_ref.
-template <class T>
+template <class T, bool VP = true>
 __device__ __forceinline__ void macros(const Consts<T>& c, const T g[NQ], T chi, T dsx, T dsy,
                                        NodeOut<T>& o) {
     const T s1234 = (g[1] + g[2]) + (g[3] + g[4]);
@@ -356,18 +380,26 @@ __device__ __forceinline__ void macros(const Consts<T>& c, const T g[NQ], T chi,
     const T jgx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const T jgy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
     const T rho = T(1) + drho;
-    const T lam = chi * c.inv_eta;
-    const T inv = recip<T>(rho * (T(1) + T(0.5) * lam));
-    const T rx = (jgx - drho * c.u0x + T(0.5) * rho * c.gx - rho * dsx) * inv;
-    const T ry = (jgy - drho * c.u0y + T(0.5) * rho * c.gy - rho * dsy) * inv;
     o.rho = rho;
     o.drho = drho;
-    o.dux = dsx + rx;
-    o.duy = dsy + ry;
+    if (VP) {
+        const T lam = chi * c.inv_eta;
+        const T inv = recip<T>(rho * (T(1) + T(0.5) * lam));
+        const T rx = (jgx - drho * c.u0x + T(0.5) * rho * c.gx - rho * dsx) * inv;
+        const T ry = (jgy - drho * c.u0y + T(0.5) * rho * c.gy - rho * dsy) * inv;
+        o.dux = dsx + rx;
+        o.duy = dsy + ry;
+        o.dFx = rho * lam * rx;
+        o.dFy = rho * lam * ry;
+    } else {  // chi = 0: plain Guo velocity, no penalization force
+        const T inv = recip<T>(rho);
+        o.dux = (jgx - drho * c.u0x + T(0.5) * rho * c.gx) * inv;
+        o.duy = (jgy - drho * c.u0y + T(0.5) * rho * c.gy) * inv;
+        o.dFx = T(0);
+        o.dFy = T(0);
+    }
     o.ux = c.u0x + o.dux;
     o.uy = c.u0y + o.duy;
-    o.dFx = rho * lam * rx;
-    o.dFy = rho * lam * ry;
     o.Gx = rho * c.gx - o.dFx;
     o.Gy = rho * c.gy - o.dFy;
     o.jgx = jgx;
@@ -379,10 +411,10 @@ __device__ __forceinline__ void macros(const Consts<T>& c, const T g[NQ], T chi,
 // F the Guo forcing vector of Eq. (12) without its (1 - 1/2tau) factor, whose moments
 // are (0, 6 u.G, -6 u.G, Gx, -Gx, Gy, -Gy, 2(ux Gx - uy Gy), ux Gy + uy Gx).
 // The conserved moments come out as rho, j + G whatever their rates.
-template <class T>
+template <class T, bool VP = true>
 __device__ __forceinline__ void collide(const Consts<T>& c, const T g[NQ], T chi, T dsx, T dsy,
                                         T out[NQ], NodeOut<T>& o) {
-    macros<T>(c, g, chi, dsx, dsy, o);
+    macros<T, VP>(c, g, chi, dsx, dsy, o);
     const T drho = o.drho, Gx = o.Gx, Gy = o.Gy;
     const T s1234 = (g[1] + g[2]) + (g[3] + g[4]);
     const T s5678 = (g[5] + g[6]) + (g[7] + g[8]);
@@ -466,10 +498,16 @@ __device__ __forceinline__ void rk4_dof(double Mq, double cq, double kq, double 
 // across the interface by streaming (the momentum-exchange force of Eqs. (25)-(27));
 // on the first step after the body is set the pre-collision momentum stands in for
 // P_in(n-1).
-__device__ inline void body_advance(const SimDesc& d, int p, const double tot[NRED]) {
-    BodyDev& B = *d.body;
-    Record r;
-    r.step = B.step;
+// Advance a body state by one step given that step's FP64 sums
+// tot = (F_vp x, y, T_vp, P_in x, y, theta after collision, the same before it), and
+// produce the step's record.  The hydrodynamic load is F_vp + P_in(n) - P_in(n-1): with
+// P_in the post-collision momentum inside the body this is, for a sharp indicator, the
+// momentum carried across the interface by streaming (the momentum-exchange force of
+// Eqs. (25)-(27)); on the first step after the body is set the pre-collision momentum
+// stands in for P_in(n-1).
+__device__ __noinline__ void state_advance(const BodyDev& B, const BodyState& prev, const double tot[NRED],
+                                     BodyState& next, Record& r) {
+    r.step = prev.step;
     r.fvp[0] = tot[0];
     r.fvp[1] = tot[1];
     r.tvp = tot[2];
@@ -478,23 +516,23 @@ __device__ inline void body_advance(const SimDesc& d, int p, const double tot[NR
     r.pin[2] = tot[5];
     double dp[3] = {0.0, 0.0, 0.0};
     if (B.imc)
-        for (int k = 0; k < 3; ++k) dp[k] = tot[3 + k] - (B.pin_valid ? B.pin_prev[k] : tot[6 + k]);
+        for (int k = 0; k < 3; ++k)
+            dp[k] = tot[3 + k] - (prev.pin_valid ? prev.pin_prev[k] : tot[6 + k]);
     r.fh[0] = tot[0] + dp[0];
     r.fh[1] = tot[1] + dp[1];
     r.th = tot[2] + dp[2];
     double q[3], v[3];
     for (int k = 0; k < 3; ++k) {
-        q[k] = B.q[p][k];
-        v[k] = B.v[p][k];
+        q[k] = prev.q[k];
+        v[k] = prev.v[k];
         r.q[k] = q[k];
         r.v[k] = v[k];
     }
-    d.hist[B.step % d.hist_cap] = r;
-    B.t_body += 1;
+    next.t_body = prev.t_body + 1;
     if (B.active) {
         if (B.mode == MODE_IMPOSED_SIN) {
             const double w = 6.283185307179586476925286766559 * B.freq;
-            const double ph = w * (double)B.t_body;
+            const double ph = w * (double)next.t_body;
             q[1] = B.y0 + B.amp * sin(ph);
             v[1] = w * B.amp * cos(ph);
         } else if (B.mode == MODE_CONST_VEL) {
@@ -509,12 +547,16 @@ __device__ inline void body_advance(const SimDesc& d, int p, const double tot[NR
         }
     }
     for (int k = 0; k < 3; ++k) {
-        B.q[p ^ 1][k] = q[k];
-        B.v[p ^ 1][k] = v[k];
-        B.pin_prev[k] = tot[3 + k];
+        next.q[k] = q[k];
+        next.v[k] = v[k];
+        next.pin_prev[k] = tot[3 + k];
     }
-    B.pin_valid = 1;
-    B.step += 1;
+    next.pin_valid = 1;
+    next.step = prev.step + 1;
+}
+
+__device__ __forceinline__ bool box_inside(const int a[4], const int b[4]) {
+    return a[0] >= b[0] && a[1] <= b[1] && a[2] >= b[2] && a[3] <= b[3];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -523,50 +565,29 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// XCD-aware placement: the hardware hands workgroup b to XCD b mod 8; renumber so
-// that each XCD receives one contiguous band of tiles (rows), keeping neighbouring
-// rows in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-    const int xcd = b & 7, local = b >> 3;
-    const int base = n >> 3, rem = n & 7;
-    return xcd < rem ? xcd * (base + 1) + local : rem * (base + 1) + (xcd - rem) * base + local;
-}
-
 // ---- one tile of one step ------------------------------------------------------------
 // A tile is TILE_X columns x ROWS rows; each lane walks down its column, issuing the
 // next row's nine loads before colliding the current row.  Nodes are pulled,
-// penalized, collided and stored; tiles that meet the body reduce force, torque and
-// internal momentum in FP64 into their slot, and the last of them to arrive sums the
-// slots in a fixed order and advances the body.
-template <class S, int ROWS>
-__device__ __forceinline__ void step_tile(const SimDesc& d, int tile, int p) {
+// penalized, collided and stored.  PART tiles (those meeting the body) also rasterise
+// chi and u_s and accumulate force, torque and internal momentum in FP64.
+template <class S, int ROWS, bool NT, bool PART>
+__device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int p,
+                                          double acc[NRED], const double* pose) {
     using T = typename Codec<S>::T;
-    __shared__ double red[NWAVE][NRED];
-    __shared__ int last;
     const Consts<T>& c = consts_of<T>(d);
     const void* fin = d.pop[p];
     char* fout = reinterpret_cast<char*>(d.pop[p ^ 1]);
-    const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
     const int i = tx * TILE_X + (int)threadIdx.x;
     const int j0 = ty * ROWS;
     const int nx = d.nx, ny = d.ny;
     const bool col_ok = i < nx;
     const bool col_inner = i >= 1 && i <= nx - 2;
-    const BodyDev& B = *d.body;
-    const double X = B.q[p][0], Y = B.q[p][1];
-    int bx0, bx1, by0, by1;
-    body_tiles(d, B, X, Y, bx0, bx1, by0, by1);
-    const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
 
     const char* P[NQ];
 #pragma unroll
     for (int a = 0; a < NQ; ++a) P[a] = plane<S>(d, fin, a);
     const unsigned rowb = (unsigned)d.pitch * (unsigned)sizeof(S);
     const float is = d.inv_scale;
-
-    double acc[NRED];
-#pragma unroll
-    for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
 
     T g[NQ], gn[NQ];
     if (col_ok && j0 < ny) {
@@ -586,47 +607,167 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tile, int p) {
                 pull_edge<S>(d, fin, i, j + 1, gn, true);
         }
         if (col_ok) {
-            double chi = 0.0, dsx = 0.0, dsy = 0.0, rx = 0.0, ry = 0.0;
-            if (part && B.active) {
-                rx = (double)i - X;
-                ry = (double)j - Y;
-                chi = disc_chi(B, disc_d2(rx, ry));
-                if (chi > 0.0) {
-                    const double om = B.v[p][2];
-                    dsx = (B.v[p][0] - om * ry) - d.u0x;
-                    dsy = (B.v[p][1] + om * rx) - d.u0y;
-                }
-            }
             T out[NQ];
             NodeOut<T> o;
-            collide<T>(c, g, (T)chi, (T)dsx, (T)dsy, out, o);
+            if (PART) {
+                const BodyDev& B = *d.body;
+                double chi = 0.0, dsx = 0.0, dsy = 0.0;
+                const double rx = (double)i - pose[0], ry = (double)j - pose[1];
+                if (B.active) {
+                    chi = disc_chi(B, disc_d2(rx, ry));
+                    if (chi > 0.0) {
+                        const double om = pose[5];
+                        dsx = (pose[3] - om * ry) - d.u0x;
+                        dsy = (pose[4] + om * rx) - d.u0y;
+                    }
+                }
+                if (chi > 0.0) {
+                    collide<T, true>(c, g, (T)chi, (T)dsx, (T)dsy, out, o);
+                    const double dFx = (double)o.dFx, dFy = (double)o.dFy;
+                    const double jx = (double)o.jgx + d.u0x, jy = (double)o.jgy + d.u0y;
+                    const double px = jx + (double)o.Gx, py = jy + (double)o.Gy;
+                    acc[0] += dFx;
+                    acc[1] += dFy;
+                    acc[2] += rx * dFy - ry * dFx;
+                    acc[3] += chi * px;
+                    acc[4] += chi * py;
+                    acc[5] += chi * (rx * py - ry * px);
+                    acc[6] += chi * jx;
+                    acc[7] += chi * jy;
+                    acc[8] += chi * (rx * jy - ry * jx);
+                } else {
+                    // outside the body: the same instructions as in other tiles (nothing
+                    // to accumulate), so results do not depend on which tiles take part
+                    collide<T, false>(c, g, T(0), T(0), T(0), out, o);
+                }
+            } else {
+                collide<T, false>(c, g, T(0), T(0), T(0), out, o);
+            }
             const unsigned off = node_off<S>(d, i, j);
 #pragma unroll
             for (int a = 0; a < NQ; ++a)
-                Codec<S>::store(fout + (long long)a * d.ps * (long long)sizeof(S), off, out[a], d.scale);
+                Codec<S>::template store<NT>(fout + (long long)a * d.ps * (long long)sizeof(S), off,
+                                             out[a], d.scale);
             if (!(o.rho > T(0)) || !__builtin_isfinite(o.ux) || !__builtin_isfinite(o.uy))
                 atomicOr(d.flag, 1);
-            if (part) {
-                const double dFx = (double)o.dFx, dFy = (double)o.dFy;
-                const double jx = (double)o.jgx + d.u0x, jy = (double)o.jgy + d.u0y;
-                const double px = jx + (double)o.Gx, py = jy + (double)o.Gy;
-                acc[0] += dFx;
-                acc[1] += dFy;
-                acc[2] += rx * dFy - ry * dFx;
-                acc[3] += chi * px;
-                acc[4] += chi * py;
-                acc[5] += chi * (rx * py - ry * px);
-                acc[6] += chi * jx;
-                acc[7] += chi * jy;
-                acc[8] += chi * (rx * jy - ry * jx);
-            }
         }
         if (r + 1 < ROWS) {
 #pragma unroll
             for (int a = 0; a < NQ; ++a) g[a] = gn[a];
         }
     }
-    if (!part) return;  // uniform over the workgroup
+}
+
+// Fixed-order FP64 sum of a step's partial slots by one workgroup of TILE_X threads;
+// every caller obtains bitwise the same totals.  Result in tot (all threads).
+__device__ __forceinline__ void sum_slots(const double* __restrict__ slots, int nb,
+                                          double red[NWAVE][NRED], double tot[NRED]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double t[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) t[k] = 0.0;
+    for (int s = threadIdx.x; s < nb; s += TILE_X)
+        for (int k = 0; k < NRED; ++k) t[k] += slots[(long long)s * NRED + k];
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) {
+        const double s = wave_sum(t[k]);
+        if (lane == 0) red[wave][k] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) {
+        double s = red[0][k];
+        for (int w = 1; w < NWAVE; ++w) s += red[w][k];
+        tot[k] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int box_count(const int b[4]) { return (b[1] - b[0] + 1) * (b[3] - b[2] + 1); }
+
+// State of step n (parity p) from the state and partial sums of step n - 1, as every
+// participating tile and the flush kernel compute it.  Thread 0 returns next/rec.
+__device__ __forceinline__ void derive_state(const SimDesc& d, int p, double red[NWAVE][NRED],
+                                             BodyState& next, Record& rec) {
+    const BodyDev& B = *d.body;
+    const BodyState& prev = B.st[p ^ 1];
+    double tot[NRED];
+    sum_slots(d.partials + (long long)(p ^ 1) * d.part_stride, box_count(prev.part_box), red, tot);
+    if (threadIdx.x == 0) {
+        state_advance(B, prev, tot, next, rec);
+        body_tiles(d.nx, d.ny, d.rows, B, next.q[0], next.q[1], next.boxM);
+        next.fresh = 0;
+        for (int k = 0; k < 4; ++k) next.part_box[k] = prev.boxM[k];
+    }
+}
+
+// Tiles that meet the body (with a margin, judged from the previous pose) obtain this
+// step's body state, rasterise chi and u_s, and reduce their FP64 sums into a slot;
+// the next step (or a flush) adds the slots in a fixed order.  No device-wide fence is
+// needed: the kernel boundary orders producer and consumer (on this multi-XCD part such
+// a fence would write back the whole L2).
+// Workgroup (bx, by) of a tiles_x x tiles_y launch handles tile column tx = bx and
+// tile row ty = (by + by0) mod tiles_y: the rows of the participation box are
+// dispatched first, so the longer body work of their tiles overlaps the rest of the
+// grid instead of extending the end of the kernel.
+template <class S, int ROWS, bool NT>
+__device__ __forceinline__ void step_tile(const SimDesc& d, int bx, int by, int p) {
+    __shared__ double red[NWAVE][NRED];
+    __shared__ double pose[6];
+    BodyDev& B = *d.body;
+    const int fresh = B.st[p].fresh;
+    const int* pb = fresh ? B.st[p].boxM : B.st[p ^ 1].boxM;
+    const int bx0 = pb[0], bx1 = pb[1], by0 = pb[2], by1 = pb[3];
+    const int tx = bx;
+    int ty = by + by0;
+    if (ty >= d.tiles_y) ty -= d.tiles_y;
+    const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
+    double acc[NRED];
+    if (!part) {
+        step_rows<S, ROWS, NT, false>(d, tx, ty, p, acc, nullptr);
+        return;  // uniform over the workgroup
+    }
+    const bool writer = tx == bx0 && ty == by0;
+    if (fresh) {
+        if (threadIdx.x < 3) {
+            pose[threadIdx.x] = B.st[p].q[threadIdx.x];
+            pose[3 + threadIdx.x] = B.st[p].v[threadIdx.x];
+        }
+    } else {
+        BodyState next;
+        Record rec;
+        derive_state(d, p, red, next, rec);
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 3; ++k) {
+                pose[k] = next.q[k];
+                pose[3 + k] = next.v[k];
+            }
+            if (writer) {
+                int exact[4];
+                body_tiles(d.nx, d.ny, d.rows, B, next.q[0], next.q[1], exact, 1.0);
+                if (!box_inside(exact, pb)) atomicOr(d.flag, 2);  // moved >= 2 nodes in a step
+                d.hist[rec.step % d.hist_cap] = rec;
+                BodyState& cur = B.st[p];
+                for (int k = 0; k < 3; ++k) {
+                    cur.q[k] = next.q[k];
+                    cur.v[k] = next.v[k];
+                    cur.pin_prev[k] = next.pin_prev[k];
+                }
+                cur.t_body = next.t_body;
+                cur.step = next.step;
+                cur.pin_valid = next.pin_valid;
+                for (int k = 0; k < 4; ++k) {
+                    cur.boxM[k] = next.boxM[k];
+                    cur.part_box[k] = next.part_box[k];
+                }
+            }
+        }
+    }
+    if (writer && threadIdx.x == 0) B.st[p ^ 1].fresh = 0;  // the next step derives its state
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+    step_rows<S, ROWS, NT, true>(d, tx, ty, p, acc, pose);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -635,43 +776,33 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tile, int p) {
         if (lane == 0) red[wave][k] = s;
     }
     __syncthreads();
-    const int nbx = bx1 - bx0 + 1;
-    const int nb = nbx * (by1 - by0 + 1);
-    if (threadIdx.x == 0) {
-        const int slot = (ty - by0) * nbx + (tx - bx0);
-        for (int k = 0; k < NRED; ++k) {
-            double s = red[0][k];
-            for (int w = 1; w < NWAVE; ++w) s += red[w][k];
-            d.partials[(long long)slot * NRED + k] = s;
-        }
-        __threadfence();
-        const unsigned prev = atomicAdd(d.counter, 1u);
-        last = (prev == (unsigned)(nb - 1));
+    if (threadIdx.x < NRED) {
+        const int k = threadIdx.x;
+        double s = red[0][k];
+        for (int w = 1; w < NWAVE; ++w) s += red[w][k];
+        const int slot = (ty - by0) * (bx1 - bx0 + 1) + (tx - bx0);
+        d.partials[(long long)p * d.part_stride + (long long)slot * NRED + k] = s;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double t[NRED];
-#pragma unroll
-    for (int k = 0; k < NRED; ++k) t[k] = 0.0;
-    for (int s = threadIdx.x; s < nb; s += TILE_X)
-        for (int k = 0; k < NRED; ++k) t[k] += d.partials[(long long)s * NRED + k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NRED; ++k) {
-        const double s = wave_sum(t[k]);
-        if (lane == 0) red[wave][k] = s;
-    }
-    __syncthreads();
+}
+
+// Flush (one workgroup): make the state of step n (parity p) final on the host's
+// request, writing the record of step n - 1.  Does nothing when the state is fresh
+// already, so it may be launched any number of times.
+__device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
+    __shared__ double red[NWAVE][NRED];
+    BodyDev& B = *d.body;
+    if (B.st[p].fresh) return;  // uniform
+    BodyState next;
+    Record rec;
+    derive_state(d, p, red, next, rec);
     if (threadIdx.x == 0) {
-        double tot[NRED];
-        for (int k = 0; k < NRED; ++k) {
-            double s = red[0][k];
-            for (int w = 1; w < NWAVE; ++w) s += red[w][k];
-            tot[k] = s;
-        }
-        body_advance(d, p, tot);
-        atomicExch(d.counter, 0u);
+        int exact[4];
+        body_tiles(d.nx, d.ny, d.rows, B, next.q[0], next.q[1], exact, 1.0);
+        if (!box_inside(exact, next.part_box)) atomicOr(d.flag, 2);
+        d.hist[rec.step % d.hist_cap] = rec;
+        next.fresh = 1;
+        for (int k = 0; k < 4; ++k) next.part_box[k] = next.boxM[k];
+        B.st[p] = next;
     }
 }
 

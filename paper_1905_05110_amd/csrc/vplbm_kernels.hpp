@@ -1,0 +1,149 @@
+// vplbm_kernels.hpp -- kernel templates of the VP-LBM library and the launch interface
+// between the host runtime (vplbm.hip) and the per-storage translation units
+// (kern_<storage>.hip), which are compiled separately and in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vplbm_device.hpp"
+
+namespace vplbm {
+
+// Launch entry points, one instantiation per storage type S (double, float,
+// _Float16, bf16s), each defined in its own translation unit.
+template <class S>
+struct Launch {
+    // the kernel of one time step (parity p; rows per tile 1, 2 or 4; nt selects
+    // nontemporal stores)
+    static void step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p, hipStream_t st);
+    static void fill(const SimDesc& d, const double g[NQ], int buf, hipStream_t st);
+    static void set_pop(const SimDesc& d, const double* f, int buf, hipStream_t st);
+    static void get_pop(const SimDesc& d, double* f, int buf, hipStream_t st);
+    static void fields(const SimDesc& d, double* out, int p, hipStream_t st);
+};
+
+// ---------------------------------------------------------------------------------
+// (A floor of 8 waves per SIMD forces spills into the body path and measured slower.)
+template <class S, int ROWS, bool NT>
+__global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ dp, int p) {
+    step_tile<S, ROWS, NT>(*dp, (int)blockIdx.x, (int)blockIdx.y, p);
+}
+
+__global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p);
+
+struct Offsets9 {
+    double g[NQ];
+};
+
+// Fill one buffer's planes with constant offsets (initial equilibrium).
+template <class S>
+__global__ void k_fill(SimDesc d, Offsets9 go, int buf) {
+    using T = typename Codec<S>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const double* g = go.g;
+    const unsigned off = node_off<S>(d, i, j);
+    for (int a = 0; a < NQ; ++a)
+        Codec<S>::template store<false>(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)g[a],
+                                        d.scale);
+}
+
+// Host FP64 populations f [9][ny][nx] <-> stored offsets.
+template <class S>
+__global__ void k_set_pop(SimDesc d, const double* __restrict__ f, int buf) {
+    using T = typename Codec<S>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const long long plane_n = (long long)d.nx * d.ny;
+    const unsigned off = node_off<S>(d, i, j);
+    for (int a = 0; a < NQ; ++a) {
+        const double v = f[a * plane_n + (long long)j * d.nx + i] - d.fref[a];
+        Codec<S>::template store<false>(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)v,
+                                        d.scale);
+    }
+}
+
+template <class S>
+__global__ void k_get_pop(SimDesc d, double* __restrict__ f, int buf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    const long long plane_n = (long long)d.nx * d.ny;
+    const unsigned off = node_off<S>(d, i, j);
+    for (int a = 0; a < NQ; ++a)
+        f[a * plane_n + (long long)j * d.nx + i] =
+            (double)Codec<S>::load(plane<S>(d, d.pop[buf], a), off, d.inv_scale) + d.fref[a];
+}
+
+// Density and penalized velocity of the current state, body at its current pose.
+template <class S>
+__global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
+    using T = typename Codec<S>::T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= d.nx) return;
+    T g[NQ];
+    pull_edge<S>(d, d.pop[p], i, j, g, false);
+    const BodyDev& B = *d.body;
+    const BodyState& st = B.st[p];  // final: the host flushes before reading fields
+    double chi = 0.0, dsx = 0.0, dsy = 0.0;
+    if (B.active) {
+        const double rx = (double)i - st.q[0], ry = (double)j - st.q[1];
+        chi = disc_chi(B, disc_d2(rx, ry));
+        if (chi > 0.0) {
+            dsx = (st.v[0] - st.v[2] * ry) - d.u0x;
+            dsy = (st.v[1] + st.v[2] * rx) - d.u0y;
+        }
+    }
+    NodeOut<T> o;
+    macros<T>(consts_of<T>(d), g, (T)chi, (T)dsx, (T)dsy, o);
+    const long long plane_n = (long long)d.nx * d.ny, o_ = (long long)j * d.nx + i;
+    out[o_] = (double)o.rho;
+    out[plane_n + o_] = d.u0x + (double)o.dux;
+    out[2 * plane_n + o_] = d.u0y + (double)o.duy;
+}
+
+
+inline dim3 grid_rows(const SimDesc& d) { return dim3((d.nx + 255) / 256, d.ny); }
+
+template <class S, bool NT>
+static void launch_step_rows(const SimDesc* dd, dim3 grid, int rows, int p, hipStream_t st) {
+    switch (rows) {
+        case 1: hipLaunchKernelGGL((k_step<S, 1, NT>), grid, dim3(TILE_X), 0, st, dd, p); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2, NT>), grid, dim3(TILE_X), 0, st, dd, p); break;
+        default: hipLaunchKernelGGL((k_step<S, 4, NT>), grid, dim3(TILE_X), 0, st, dd, p); break;
+    }
+}
+
+// Body of one translation unit: defines Launch<S>.
+#define VPLBM_DEFINE_LAUNCH(S)                                                                \
+    template <>                                                                             \
+    void Launch<S>::step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p,            \
+                         hipStream_t st) {                                                  \
+        if (nt)                                                                             \
+            launch_step_rows<S, true>(dd, grid, rows, p, st);                               \
+        else                                                                                \
+            launch_step_rows<S, false>(dd, grid, rows, p, st);                              \
+    }                                                                                       \
+    template <>                                                                             \
+    void Launch<S>::fill(const SimDesc& d, const double g[NQ], int buf, hipStream_t st) {   \
+        Offsets9 go;                                                                        \
+        for (int a = 0; a < NQ; ++a) go.g[a] = g[a];                                        \
+        hipLaunchKernelGGL(k_fill<S>, grid_rows(d), dim3(256), 0, st, d, go, buf);          \
+    }                                                                                       \
+    template <>                                                                             \
+    void Launch<S>::set_pop(const SimDesc& d, const double* f, int buf, hipStream_t st) {   \
+        hipLaunchKernelGGL(k_set_pop<S>, grid_rows(d), dim3(256), 0, st, d, f, buf);        \
+    }                                                                                       \
+    template <>                                                                             \
+    void Launch<S>::get_pop(const SimDesc& d, double* f, int buf, hipStream_t st) {         \
+        hipLaunchKernelGGL(k_get_pop<S>, grid_rows(d), dim3(256), 0, st, d, f, buf);        \
+    }                                                                                       \
+    template <>                                                                             \
+    void Launch<S>::fields(const SimDesc& d, double* out, int p, hipStream_t st) {          \
+        hipLaunchKernelGGL(k_fields<S>, grid_rows(d), dim3(256), 0, st, d, out, p);         \
+    }
+
+}  // namespace vplbm

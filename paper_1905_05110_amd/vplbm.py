@@ -23,8 +23,8 @@ MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
 EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
            "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
            "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
-           "lbm_step_index", "lbm_step_timed", "lbm_save", "lbm_load", "lbm_destroy",
-           "lbm_last_error"]
+           "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_save", "lbm_load",
+           "lbm_destroy", "lbm_last_error"]
 
 
 class LbmError(RuntimeError):
@@ -42,7 +42,8 @@ class Opts(C.Structure):
     _fields_ = [("bc", C.c_int * 4), ("u_wall", (C.c_double * 2) * 4), ("u_conv", C.c_double),
                 ("g_fluid", C.c_double * 2), ("rho0", C.c_double), ("u0", C.c_double * 2),
                 ("storage", C.c_int), ("fp16_scale_log2", C.c_int), ("history_cap", C.c_int),
-                ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("hip_stream", C.c_void_p),
+                ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
+                ("hip_stream", C.c_void_p),
                 ("pop_buffers", C.c_void_p * 2)]
 
 
@@ -91,6 +92,8 @@ def load_library(path=LIB_PATH):
     L.lbm_step_index.argtypes = [P]
     L.lbm_step_index.restype = C.c_int64
     L.lbm_step_timed.argtypes = [P, C.c_int64, _DP, _DP]
+    L.lbm_autotune.argtypes = [P, C.c_int, C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_double)]
     L.lbm_save.argtypes = [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbm_load.argtypes = [P, C.c_void_p, C.c_size_t]
     L.lbm_destroy.argtypes = [P]
@@ -126,6 +129,7 @@ def make_opts(spec, stream=None, buffers=None, history_cap=65536):
     o.history_cap = int(history_cap)
     o.offset_ref = {"initial": 0, "rest": 1}[spec.get("offset_ref", "initial")]
     o.rows_per_tile = int(spec.get("rows_per_tile", 0))
+    o.store_mode = {"auto": 0, "plain": 1, "nontemporal": 2}[spec.get("store_mode", "auto")]
     o.hip_stream = stream
     if buffers is not None:
         o.pop_buffers[0], o.pop_buffers[1] = buffers
@@ -248,6 +252,14 @@ class Sim:
         k, r = C.c_double(), C.c_double()
         self._check(self.L.lbm_step_timed(self.h, int(n), C.byref(k), C.byref(r)))
         return k.value, r.value
+
+    def autotune(self, trial_steps=20, cache=None):
+        """Pick rows per tile and store mode by timing; returns (rows, nt, us/step)."""
+        r, n, us = C.c_int(), C.c_int(), C.c_double()
+        path = cache.encode() if cache else None
+        self._check(self.L.lbm_autotune(self.h, int(trial_steps), path, C.byref(r), C.byref(n),
+                                        C.byref(us)))
+        return r.value, n.value, us.value
 
     def save(self):
         size = C.c_size_t()
