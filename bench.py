@@ -10,6 +10,13 @@ region, the step kernel's achieved HBM bandwidth against the 8 TB/s peak, and th
 CPU oracle timed on a bounded sample of the same workload on the host cores.  A step is
 exactly one kernel launch (replayed from captured HIP graphs), so the kernel's average
 duration is the timed region's event-measured time divided by the number of launches.
+
+``--workload batch_sweep`` times the batched path instead: 64 free-VIV runs of uneven
+size (ny drawn from U{128..512} with seed 0, nx = 2 ny, D = ny/12, U_r from 2 to 12),
+all advanced by one launch per step.  ``--accuracy-steps N`` then also runs the sweep
+for N steps in every storage precision and reports, per precision, the relative error
+of each run's mean drag coefficient and RMS lift coefficient over the second half of
+the run against the FP64 runs.
 """
 import argparse
 import json
@@ -27,6 +34,9 @@ BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}  # 9 reads + 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="free_viv", choices=("free_viv", "batch_sweep"))
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="batch_sweep: also compare storages over this many steps")
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--storage", default="fp32", choices=sorted(BYTES_PER_NODE))
@@ -90,12 +100,148 @@ def traffic_for(path, storage, nx, ny, rows, nt):
     return None
 
 
+def cpu_baseline_batch(sweep, target_seconds):
+    """FP64 CPU oracle on the sweep's runs, smallest first, for a bounded time."""
+    from oracle import oracle as orc
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    orc.set_threads(cores)
+    nodes_done, dt, used = 0, 0.0, []
+    for w in sorted(sweep, key=lambda w: w["spec"]["nx"] * w["spec"]["ny"]):
+        sim = orc.OracleSim(w["spec"], w["body"])
+        sim.step(1)
+        t0 = time.perf_counter()
+        sim.step(20)
+        dt += time.perf_counter() - t0
+        nodes_done += w["spec"]["nx"] * w["spec"]["ny"] * 20
+        used.append(w["name"])
+        if dt > target_seconds:
+            break
+    return {"value": round(nodes_done / dt / 1e6, 2), "unit": "MLUPS", "cores": orc.max_threads(),
+            "kind": "oracle",
+            "sample": "20 steps of each of the %d smallest runs of the sweep (FP64 oracle, %.1f s)"
+                      % (len(used), dt)}
+
+
+def sweep_statistics(batch, sweep, steps):
+    """Mean C_D and RMS C_L (from the hydrodynamic force) over the second half."""
+    import numpy as np
+    out = []
+    for m, w in zip(batch.sims, sweep):
+        r = m.forces(cap=steps)
+        assert len(r) == steps, (w["name"], len(r))
+        h = r[steps // 2:]
+        scale = 0.5 * w["U0"] ** 2 * w["D"]
+        cd = h["fh"][:, 0] / scale
+        cl = h["fh"][:, 1] / scale
+        out.append((float(cd.mean()), float(np.sqrt((cl ** 2).mean()))))
+    return out
+
+
+def batch_accuracy(args, vplbm, W):
+    import numpy as np
+    res = {}
+    for storage in ("fp64", "fp32", "fp16", "bf16"):
+        sweep = W.batch_sweep(storage=storage)
+        members = [(w["spec"], w["body"]) for w in sweep]
+        print("accuracy run %s, %d steps" % (storage, args.accuracy_steps), file=sys.stderr,
+              flush=True)
+        batch = vplbm.Batch(members, storage=storage, graph_steps=64,
+                            history_cap=args.accuracy_steps)
+        batch.step(args.accuracy_steps)
+        batch.sync()
+        res[storage] = sweep_statistics(batch, sweep, args.accuracy_steps)
+        batch.close()
+    ref = np.array(res["fp64"])
+    out = {"steps": args.accuracy_steps, "fp64_mean_cd_range": [round(ref[:, 0].min(), 4),
+                                                                  round(ref[:, 0].max(), 4)],
+           "fp64_rms_cl_range": [round(ref[:, 1].min(), 4), round(ref[:, 1].max(), 4)]}
+    for storage in ("fp32", "fp16", "bf16"):
+        a = np.array(res[storage])
+        ecd = np.abs(a[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+        ecl = np.abs(a[:, 1] - ref[:, 1]) / np.maximum(np.abs(ref[:, 1]), 1e-300)
+        out[storage] = {"mean_cd_rel_err_max": float("%.3g" % ecd.max()),
+                        "mean_cd_rel_err_median": float("%.3g" % np.median(ecd)),
+                        "rms_cl_rel_err_max": float("%.3g" % ecl.max()),
+                        "rms_cl_rel_err_median": float("%.3g" % np.median(ecl))}
+    return out
+
+
+def run_batch(args):
+    import torch
+    from paper_1905_05110_amd import workloads as W
+    from paper_1905_05110_amd import vplbm
+
+    sweep = W.batch_sweep(storage=args.storage)
+    members = [(w["spec"], w["body"]) for w in sweep]
+    nodes = sum(s["nx"] * s["ny"] for s, _ in members)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        rows = args.rows if args.rows else 0
+        batch = vplbm.Batch(members, storage=args.storage, rows=rows, store=args.store,
+                            history_cap=4096, stream=stream.cuda_stream)
+        tuned = None
+        if not args.no_autotune and args.rows == 0 and args.store == "auto":
+            print("autotune", file=sys.stderr, flush=True)
+            tuned = batch.autotune(trial_steps=20)
+        if args.graph_steps:
+            batch.set_graph_steps(args.graph_steps)
+        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+        batch.step(args.warmup)
+        batch.sync()
+        torch.cuda.synchronize()
+        print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        batch.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        region_ms = e0.elapsed_time(e1)
+        batch.sync()
+        batch.close()
+    ms_per_step = region_ms / args.steps
+    mlups = nodes * args.steps / (region_ms * 1e-3) / 1e6
+    avg_kernel_s = region_ms * 1e-3 / args.steps
+    bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
+    achieved = bytes_per_launch / avg_kernel_s / 1e9
+    order_names = {0: "given", 1: "largest_first", 2: "interleaved"}
+    out = {
+        "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step, batched runs)",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f32 (fp16 storage)",
+                  "bf16": "f32 (bf16 storage)"}[args.storage],
+        "data": "synthetic (lattice flows from a uniform inflow state; no dataset)",
+        "config": {"workload": "batch_sweep_64", "runs": len(members), "nodes": nodes,
+                   "storage": args.storage, "graph_steps": args.graph_steps,
+                   "rows_per_tile": tuned[0] if tuned else args.rows,
+                   "nontemporal_stores": bool(tuned[1]) if tuned else args.store,
+                   "order": order_names[tuned[2]] if tuned else "largest_first"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_step<%s> (batched)" % args.storage,
+                     "avg_kernel_us": round(avg_kernel_s * 1e6, 3),
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "wall_s": round(wall, 3),
+    }
+    if args.accuracy_steps:
+        out["accuracy_vs_fp64"] = batch_accuracy(args, vplbm, W)
+    if not args.no_cpu_baseline:
+        print("cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_batch(sweep, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch_sweep":
+        return run_batch(args)
     import torch
     from paper_1905_05110_amd import workloads as W
     from paper_1905_05110_amd import vplbm

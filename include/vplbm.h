@@ -185,7 +185,9 @@ int lbm_sync(lbm_sim* sim);
 
 /* Synchronises, then copies the records of the steps not yet drained, oldest first,
  * at most cap of them, into out; *n_out receives the count.  Records overwritten on
- * the device before being drained (more than history_cap pending) are skipped. */
+ * the device before being drained (more than history_cap pending) are skipped.  Steps
+ * taken without a body have no record; setting a body on a simulation that has none
+ * discards records still pending from an earlier body. */
 int lbm_forces(lbm_sim* sim, lbm_force_rec* out, int64_t cap, int64_t* n_out);
 
 /* Synchronises, then writes density and penalized velocity (Eq. (22)) of the current
@@ -224,6 +226,69 @@ int lbm_autotune(lbm_sim* sim, int trial_steps, const char* cache_path, int* row
  * from a simulation of the same grid and storage. */
 int lbm_save(lbm_sim* sim, void* buf, size_t cap, size_t* size_out);
 int lbm_load(lbm_sim* sim, const void* buf, size_t size);
+
+/* ---- batches: many independent simulations advanced by one launch per step ----------
+ * All simulations of a batch share the storage precision and the launch configuration
+ * (rows per tile, store mode); each keeps its own grid, rates, boundaries, body,
+ * buffers and FP64 reductions, so a simulation inside a batch computes bitwise the same
+ * as alone with the same configuration.  One launch per step covers every tile of every
+ * simulation, in an order (schedule) chosen at creation or by lbm_batch_autotune:
+ *   GIVEN          simulation by simulation, in the order given;
+ *   LARGEST_FIRST  simulation by simulation, largest grid first (default);
+ *   INTERLEAVED    one row of tiles from each simulation in turn. */
+typedef struct lbm_batch lbm_batch;
+enum { LBM_ORDER_GIVEN = 0, LBM_ORDER_LARGEST_FIRST = 1, LBM_ORDER_INTERLEAVED = 2 };
+
+typedef struct {
+    int nx, ny;
+    lbm_rates rates;
+    double eta;
+    const lbm_opts* opts;  /* may be NULL; its storage, stream, buffers and launch fields are
+                              replaced by the batch's */
+    const lbm_body* body;  /* may be NULL (no body) */
+} lbm_batch_desc;
+
+typedef struct {
+    int storage;        /* LBM_FP64 / LBM_FP32 / LBM_FP16_OFS / LBM_BF16_OFS */
+    int rows_per_tile;  /* 0 (default), 1, 2 or 4 */
+    int store_mode;     /* LBM_STORE_* */
+    int order;          /* LBM_ORDER_* */
+    void* hip_stream;   /* NULL: the library creates one */
+} lbm_batch_opts;
+
+void lbm_default_batch_opts(lbm_batch_opts* o);
+
+/* Creates n >= 1 simulations (each argument checked as by lbm_create and lbm_set_body).
+ * On failure nothing is left allocated and lbm_batch_last_error(NULL) tells why. */
+int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* opts,
+                     lbm_batch** out);
+
+/* Enqueues n steps of every simulation (one kernel launch per step, or captured graphs
+ * of k steps after lbm_batch_set_graph_steps(k), k even). */
+int lbm_batch_step(lbm_batch* batch, int64_t n);
+int lbm_batch_set_graph_steps(lbm_batch* batch, int k);
+
+/* Waits for the batch; LBM_ERR_UNSTABLE if any simulation met an unstable state. */
+int lbm_batch_sync(lbm_batch* batch);
+
+/* Handle of member i, owned by the batch.  It serves lbm_forces, lbm_fields,
+ * lbm_get_body_state, lbm_get/set_populations, lbm_set/clear_body, lbm_sync, lbm_save,
+ * lbm_step_index; lbm_step, lbm_step_timed, lbm_set_graph_steps, lbm_autotune, lbm_load
+ * and lbm_destroy return LBM_ERR_STATE on it. */
+int lbm_batch_sim(lbm_batch* batch, int i, lbm_sim** out);
+int lbm_batch_size(const lbm_batch* batch);
+
+/* Sets the launch configuration: rows 1/2/4, LBM_STORE_PLAIN or _NONTEMPORAL, order. */
+int lbm_batch_configure(lbm_batch* batch, int rows, int store_mode, int order);
+
+/* Chooses rows, store mode and order by timing trial_steps steps of each candidate on a
+ * scratch copy of the batch, then applies them (members' states are not touched).
+ * Outputs may be NULL; us_out is the time per batch step in microseconds. */
+int lbm_batch_autotune(lbm_batch* batch, int trial_steps, int* rows_out, int* nt_out,
+                       int* order_out, double* us_out);
+
+int lbm_batch_destroy(lbm_batch* batch);
+const char* lbm_batch_last_error(const lbm_batch* batch);
 
 /* Frees everything the library allocated for the simulation. */
 int lbm_destroy(lbm_sim* sim);

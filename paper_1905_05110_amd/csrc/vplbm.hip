@@ -67,6 +67,7 @@ struct lbm_sim {
     bool own_stream = false;
     int64_t host_step = 0;
     int64_t drained = 0;
+    int64_t rec_end = 0;  // without a body: records exist for the steps before this one
     int hist_cap = 65536;
     lbm_opts opts{};
     lbm_rates rates{};
@@ -80,6 +81,7 @@ struct lbm_sim {
     bool nt = false;  // nontemporal population stores
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
+    bool in_batch = false;  // member of an lbm_batch: stepped, configured and freed by it
 };
 
 #define HIP_TRY(sim, expr)                                                             \
@@ -94,6 +96,10 @@ struct lbm_sim {
 static int fail(lbm_sim* s, int code, const std::string& msg) {
     if (s) s->err = msg;
     return code;
+}
+
+static int reject_member(lbm_sim* s) {
+    return fail(s, LBM_ERR_STATE, "a member of a batch is stepped, configured and freed by its batch");
 }
 
 
@@ -402,6 +408,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
 
 int lbm_destroy(lbm_sim* s) {
     if (!s) return LBM_ERR_ARG;
+    if (s->in_batch) return reject_member(s);
     hipStreamSynchronize(s->stream);
     free_sim(s);
     return LBM_OK;
@@ -479,6 +486,7 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
     s->body_h = B;
     s->body_desc = *b;
+    if (!s->has_body) s->drained = std::max(s->drained, s->host_step);  // body-less steps
     s->has_body = true;
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     return LBM_OK;
@@ -496,6 +504,7 @@ int lbm_clear_body(lbm_sim* s) {
     st.pin_valid = 0;
     st.fresh = 1;
     for (int k = 0; k < 4; ++k) st.boxM[k] = st.part_box[k] = 0;
+    if (s->has_body) s->rec_end = s->host_step;
     s->has_body = false;
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     return LBM_OK;
@@ -503,6 +512,7 @@ int lbm_clear_body(lbm_sim* s) {
 
 int lbm_set_graph_steps(lbm_sim* s, int k) {
     if (!s) return LBM_ERR_ARG;
+    if (s->in_batch) return reject_member(s);
     if (k != 0 && (k < 2 || (k & 1))) return fail(s, LBM_ERR_ARG, "graph steps must be 0 or even >= 2");
     drop_graph(s);
     s->graph_steps = k;
@@ -531,6 +541,7 @@ static int capture_graph(lbm_sim* s) {
 
 int lbm_step(lbm_sim* s, int64_t n) {
     if (!s) return LBM_ERR_ARG;
+    if (s->in_batch) return reject_member(s);
     if (n < 0) return fail(s, LBM_ERR_ARG, "n must be >= 0");
     int64_t done = 0;
     if (s->graph_steps > 0 && n >= s->graph_steps) {
@@ -558,6 +569,7 @@ int lbm_step(lbm_sim* s, int64_t n) {
 
 int lbm_step_timed(lbm_sim* s, int64_t n, double* kernel_ms, double* region_ms) {
     if (!s || n < 0) return fail(s, LBM_ERR_ARG, "bad argument");
+    if (s->in_batch) return reject_member(s);
     std::vector<hipEvent_t> ev(2 * (size_t)n + 2);
     for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
     HIP_TRY(s, hipEventRecord(ev[0], s->stream));
@@ -585,7 +597,7 @@ int lbm_forces(lbm_sim* s, lbm_force_rec* out, int64_t cap, int64_t* n_out) {
     if (!s || (!out && cap > 0) || cap < 0) return fail(s, LBM_ERR_ARG, "bad argument");
     int rc = sync_check(s);  // flushes: records exist for every enqueued step
     if (n_out) *n_out = 0;
-    const int64_t written = s->host_step;
+    const int64_t written = s->has_body ? s->host_step : s->rec_end;
     if (s->drained < written - s->hist_cap) s->drained = written - s->hist_cap;
     int64_t n = std::min<int64_t>(written - s->drained, cap);
     static_assert(sizeof(Record) == sizeof(lbm_force_rec), "record layout");
@@ -722,6 +734,7 @@ static bool tune_lookup(const char* path, const std::string& key, int& rows, int
 int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_out, int* nt_out,
                  double* us_out) {
     if (!s || trial_steps < 1) return fail(s, LBM_ERR_ARG, "bad argument");
+    if (s->in_batch) return reject_member(s);
     const std::string key = tune_key(s);
     int rows = 0, nt = 0;
     double best = -1.0;
@@ -820,6 +833,7 @@ int lbm_save(lbm_sim* s, void* buf, size_t cap, size_t* size_out) {
 
 int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     if (!s || !buf) return fail(s, LBM_ERR_ARG, "NULL argument");
+    if (s->in_batch) return reject_member(s);
     if (size < sizeof(SaveHeader)) return fail(s, LBM_ERR_ARG, "buffer too small");
     SaveHeader h;
     std::memcpy(&h, buf, sizeof(h));
@@ -838,9 +852,406 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     HIP_TRY(s, hipMemcpy(s->outlet, c, ob, hipMemcpyHostToDevice));
     c += ob;
     HIP_TRY(s, hipMemcpy(s->body_d, c, sizeof(BodyDev), hipMemcpyHostToDevice));
+    BodyDev B;
+    std::memcpy(&B, c, sizeof(B));
+    s->has_body = B.active != 0;
+    if (!s->has_body) s->rec_end = s->drained = std::max(s->drained, s->host_step);
     HIP_TRY(s, hipMemset(s->flag, 0, sizeof(int)));
     drop_graph(s);
     return LBM_OK;
+}
+
+}  // extern "C"
+
+// ---- batches of independent simulations -------------------------------------------------
+struct lbm_batch {
+    int n = 0;
+    int storage = LBM_FP32;
+    std::vector<lbm_sim*> sims;
+    std::vector<lbm_batch_desc> in;  // creation inputs (for the autotuner's scratch batch)
+    std::vector<lbm_opts> in_opts;
+    std::vector<lbm_body> in_body;
+    std::vector<int> has_body;
+    lbm_batch_opts bopts{};
+    SimDesc* descs_d = nullptr;
+    int2* sched_d = nullptr;
+    int nsched = 0;
+    int order = LBM_ORDER_LARGEST_FIRST;
+    int rows = 1;
+    bool nt = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t host_step = 0;
+    int graph_steps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string err;
+};
+
+static thread_local std::string g_batch_create_error;
+
+static int bfail(lbm_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIP_TRY(b, expr)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            (b)->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return LBM_ERR_HIP;                                                         \
+        }                                                                               \
+    } while (0)
+
+static void batch_drop_graph(lbm_batch* b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+// Work list of one step: every tile of every simulation once, in the chosen order.
+static std::vector<int2> batch_schedule(const lbm_batch* b, int order) {
+    std::vector<int> idx(b->n);
+    for (int i = 0; i < b->n; ++i) idx[i] = i;
+    auto tiles = [&](int i) {
+        return (long long)b->sims[i]->desc.tiles_x * b->sims[i]->desc.tiles_y;
+    };
+    if (order == LBM_ORDER_LARGEST_FIRST)
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return tiles(a) > tiles(c); });
+    std::vector<int2> out;
+    if (order == LBM_ORDER_INTERLEAVED) {
+        // one row of tiles from each simulation in turn
+        int maxr = 0;
+        for (int i = 0; i < b->n; ++i) maxr = std::max(maxr, b->sims[i]->desc.tiles_y);
+        for (int r = 0; r < maxr; ++r)
+            for (int i = 0; i < b->n; ++i) {
+                const SimDesc& d = b->sims[i]->desc;
+                if (r >= d.tiles_y) continue;
+                for (int x = 0; x < d.tiles_x; ++x) out.push_back(make_int2(i, (r << 16) | x));
+            }
+        return out;
+    }
+    for (int i : idx) {
+        const SimDesc& d = b->sims[i]->desc;
+        for (int r = 0; r < d.tiles_y; ++r)
+            for (int x = 0; x < d.tiles_x; ++x) out.push_back(make_int2(i, (r << 16) | x));
+    }
+    return out;
+}
+
+static int batch_upload(lbm_batch* b) {
+    std::vector<SimDesc> ds(b->n);
+    for (int i = 0; i < b->n; ++i) ds[i] = b->sims[i]->desc;
+    BHIP_TRY(b, hipMemcpy(b->descs_d, ds.data(), ds.size() * sizeof(SimDesc), hipMemcpyHostToDevice));
+    std::vector<int2> sc = batch_schedule(b, b->order);
+    if (b->sched_d) (void)hipFree(b->sched_d);
+    b->sched_d = nullptr;
+    BHIP_TRY(b, hipMalloc((void**)&b->sched_d, sc.size() * sizeof(int2)));
+    BHIP_TRY(b, hipMemcpy(b->sched_d, sc.data(), sc.size() * sizeof(int2), hipMemcpyHostToDevice));
+    b->nsched = (int)sc.size();
+    batch_drop_graph(b);
+    return LBM_OK;
+}
+
+static int batch_launch(lbm_batch* b) {
+    const int p = (int)(b->host_step & 1);
+    dispatch(b->storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        Launch<S>::step_batch(b->descs_d, b->sched_d, b->nsched, b->rows, b->nt, p, b->stream);
+        return 0;
+    });
+    BHIP_TRY(b, hipGetLastError());
+    b->host_step += 1;
+    for (lbm_sim* s : b->sims) s->host_step += 1;
+    return LBM_OK;
+}
+
+static void batch_free(lbm_batch* b) {
+    batch_drop_graph(b);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (lbm_sim* s : b->sims)
+        if (s) free_sim(s);
+    if (b->descs_d) (void)hipFree(b->descs_d);
+    if (b->sched_d) (void)hipFree(b->sched_d);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+extern "C" {
+
+void lbm_default_batch_opts(lbm_batch_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->storage = LBM_FP32;
+    o->order = LBM_ORDER_LARGEST_FIRST;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) {
+    return b ? b->err.c_str() : g_batch_create_error.c_str();
+}
+
+int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* opts,
+                     lbm_batch** out) {
+    if (!out || !descs || n < 1) return g_batch_create_error = "bad argument", LBM_ERR_ARG;
+    *out = nullptr;
+    lbm_batch_opts bo;
+    if (opts)
+        bo = *opts;
+    else
+        lbm_default_batch_opts(&bo);
+    if (bo.order < LBM_ORDER_GIVEN || bo.order > LBM_ORDER_INTERLEAVED)
+        return g_batch_create_error = "unknown order", LBM_ERR_ARG;
+    if (bo.store_mode < LBM_STORE_AUTO || bo.store_mode > LBM_STORE_NONTEMPORAL)
+        return g_batch_create_error = "unknown store mode", LBM_ERR_ARG;
+    if (bo.storage < LBM_FP64 || bo.storage > LBM_BF16_OFS)
+        return g_batch_create_error = "unknown storage", LBM_ERR_ARG;
+    if (bo.rows_per_tile != 0 && bo.rows_per_tile != 1 && bo.rows_per_tile != 2 && bo.rows_per_tile != 4)
+        return g_batch_create_error = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
+    lbm_batch* b = new lbm_batch();
+    b->n = n;
+    b->storage = bo.storage;
+    b->bopts = bo;
+    b->order = bo.order;
+    auto bail = [&](int code) {
+        g_batch_create_error = b->err;
+        batch_free(b);
+        return code;
+    };
+    if (bo.hip_stream) {
+        b->stream = (hipStream_t)bo.hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return b->err = hipGetErrorString(e), bail(LBM_ERR_HIP);
+        b->own_stream = true;
+    }
+    b->in.assign(descs, descs + n);
+    b->in_opts.resize(n);
+    b->in_body.resize(n);
+    b->has_body.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        lbm_opts o;
+        if (descs[i].opts)
+            o = *descs[i].opts;
+        else
+            lbm_default_opts(&o);
+        o.storage = bo.storage;
+        o.hip_stream = b->stream;
+        o.pop_buffers[0] = o.pop_buffers[1] = nullptr;
+        o.rows_per_tile = bo.rows_per_tile;
+        o.store_mode = bo.store_mode;
+        b->in_opts[i] = o;
+        if (descs[i].body) {
+            b->in_body[i] = *descs[i].body;
+            b->has_body[i] = 1;
+        }
+        lbm_sim* s = nullptr;
+        int rc = lbm_create(descs[i].nx, descs[i].ny, descs[i].rates, descs[i].eta, &o, &s);
+        if (rc) return b->err = "simulation " + std::to_string(i) + ": " + lbm_last_error(nullptr), bail(rc);
+        s->in_batch = true;
+        b->sims.push_back(s);
+        if (descs[i].body) {
+            rc = lbm_set_body(s, descs[i].body);
+            if (rc) return b->err = "simulation " + std::to_string(i) + ": " + s->err, bail(rc);
+        }
+        if (s->desc.tiles_x > 0xffff || s->desc.tiles_y > 0x7fff)
+            return b->err = "grid too large for a batch", bail(LBM_ERR_ARG);
+    }
+    // one launch configuration for the whole batch; the defaults follow the single-grid
+    // rules applied to the batch's total size
+    long long nodes = 0;
+    size_t bytes = 0;
+    for (lbm_sim* s : b->sims) {
+        nodes += (long long)s->nx * s->ny;
+        bytes += s->pop_bytes;
+    }
+    b->rows = bo.rows_per_tile ? bo.rows_per_tile
+                               : ((bo.storage != LBM_FP64 && nodes <= 2500000) ? 2 : 1);
+    b->nt = bo.store_mode == LBM_STORE_NONTEMPORAL ||
+            (bo.store_mode == LBM_STORE_AUTO && 2 * bytes > (size_t(1) << 30));
+    for (lbm_sim* s : b->sims) {
+        int rc = apply_launch_config(s, b->rows, b->nt);
+        if (rc) return b->err = s->err, bail(rc);
+    }
+    hipError_t e = hipMalloc((void**)&b->descs_d, (size_t)n * sizeof(SimDesc));
+    if (e != hipSuccess) return b->err = hipGetErrorString(e), bail(LBM_ERR_ALLOC);
+    int rc = batch_upload(b);
+    if (rc) return bail(rc);
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_ERR_ARG;
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    return LBM_OK;
+}
+
+int lbm_batch_size(const lbm_batch* b) { return b ? b->n : -1; }
+
+int lbm_batch_sim(lbm_batch* b, int i, lbm_sim** out) {
+    if (!b || !out || i < 0 || i >= b->n) return bfail(b, LBM_ERR_ARG, "bad argument");
+    *out = b->sims[i];
+    return LBM_OK;
+}
+
+int lbm_batch_set_graph_steps(lbm_batch* b, int k) {
+    if (!b) return LBM_ERR_ARG;
+    if (k != 0 && (k < 2 || (k & 1))) return bfail(b, LBM_ERR_ARG, "graph steps must be 0 or even >= 2");
+    batch_drop_graph(b);
+    b->graph_steps = k;
+    return LBM_OK;
+}
+
+static int batch_capture(lbm_batch* b) {
+    const int64_t saved = b->host_step;
+    std::vector<int64_t> saved_s(b->n);
+    for (int i = 0; i < b->n; ++i) saved_s[i] = b->sims[i]->host_step;
+    b->host_step = 0;
+    BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_OK;
+    for (int k = 0; k < b->graph_steps && rc == LBM_OK; ++k) rc = batch_launch(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    b->host_step = saved;
+    for (int i = 0; i < b->n; ++i) b->sims[i]->host_step = saved_s[i];
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return bfail(b, LBM_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    BHIP_TRY(b, hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t n) {
+    if (!b) return LBM_ERR_ARG;
+    if (n < 0) return bfail(b, LBM_ERR_ARG, "n must be >= 0");
+    for (lbm_sim* s : b->sims)
+        if (s->host_step != b->host_step)
+            return bfail(b, LBM_ERR_STATE, "a simulation of the batch was stepped on its own");
+    int64_t done = 0;
+    if (b->graph_steps > 0 && n >= b->graph_steps) {
+        if (b->host_step & 1) {
+            int rc = batch_launch(b);
+            if (rc) return rc;
+            ++done;
+        }
+        if (!b->gexec) {
+            int rc = batch_capture(b);
+            if (rc) return rc;
+        }
+        while (n - done >= b->graph_steps) {
+            BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+            b->host_step += b->graph_steps;
+            for (lbm_sim* s : b->sims) s->host_step += b->graph_steps;
+            done += b->graph_steps;
+        }
+    }
+    for (; done < n; ++done) {
+        int rc = batch_launch(b);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_sync(lbm_batch* b) {
+    if (!b) return LBM_ERR_ARG;
+    int worst = LBM_OK;
+    for (lbm_sim* s : b->sims) {
+        int rc = sync_check(s);
+        if (rc == LBM_ERR_UNSTABLE && worst == LBM_OK) worst = rc;
+        if (rc && rc != LBM_ERR_UNSTABLE) return bfail(b, rc, s->err);
+    }
+    return worst;
+}
+
+static int batch_apply(lbm_batch* b, int rows, bool nt, int order) {
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    for (lbm_sim* s : b->sims) {
+        int rc = apply_launch_config(s, rows, nt);
+        if (rc) return bfail(b, rc, s->err);
+    }
+    b->rows = rows;
+    b->nt = nt;
+    b->order = order;
+    return batch_upload(b);
+}
+
+// Times trial_steps steps of a scratch copy of the batch for each candidate.
+static int batch_time(lbm_batch* b, int rows, bool nt, int order, int trial_steps, double& us) {
+    lbm_batch_opts bo = b->bopts;
+    bo.hip_stream = nullptr;
+    bo.rows_per_tile = rows;
+    bo.store_mode = nt ? LBM_STORE_NONTEMPORAL : LBM_STORE_PLAIN;
+    bo.order = order;
+    std::vector<lbm_batch_desc> ds = b->in;
+    for (int i = 0; i < b->n; ++i) {
+        b->in_opts[i].history_cap = 64;
+        ds[i].opts = &b->in_opts[i];
+        ds[i].body = b->has_body[i] ? &b->in_body[i] : nullptr;
+    }
+    lbm_batch* t = nullptr;
+    int rc = lbm_batch_create(b->n, ds.data(), &bo, &t);
+    if (rc) return bfail(b, rc, std::string("autotune: ") + lbm_batch_last_error(nullptr));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.f;
+    bool ok = lbm_batch_step(t, 3) == LBM_OK && hipEventCreate(&e0) == hipSuccess &&
+              hipEventCreate(&e1) == hipSuccess && hipEventRecord(e0, t->stream) == hipSuccess &&
+              lbm_batch_step(t, trial_steps) == LBM_OK &&
+              hipEventRecord(e1, t->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+              hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    lbm_batch_destroy(t);
+    if (!ok) return bfail(b, LBM_ERR_HIP, "autotune: timing run failed");
+    us = 1e3 * ms / trial_steps;
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* rows_out, int* nt_out, int* order_out,
+                       double* us_out) {
+    if (!b || trial_steps < 1) return bfail(b, LBM_ERR_ARG, "bad argument");
+    int best_rows = 1, best_order = LBM_ORDER_LARGEST_FIRST;
+    bool best_nt = false;
+    double best = -1.0, us = 0.0;
+    const int cand_rows[3] = {1, 2, 4};
+    for (int ci = 0; ci < 6; ++ci) {
+        int rc = batch_time(b, cand_rows[ci / 2], ci & 1, LBM_ORDER_LARGEST_FIRST, trial_steps, us);
+        if (rc) return rc;
+        if (best < 0 || us < best) {
+            best = us;
+            best_rows = cand_rows[ci / 2];
+            best_nt = ci & 1;
+        }
+    }
+    for (int order : {LBM_ORDER_GIVEN, LBM_ORDER_INTERLEAVED}) {
+        int rc = batch_time(b, best_rows, best_nt, order, trial_steps, us);
+        if (rc) return rc;
+        if (us < best) {
+            best = us;
+            best_order = order;
+        }
+    }
+    int rc = batch_apply(b, best_rows, best_nt, best_order);
+    if (rc) return rc;
+    if (rows_out) *rows_out = best_rows;
+    if (nt_out) *nt_out = best_nt;
+    if (order_out) *order_out = best_order;
+    if (us_out) *us_out = best;
+    return LBM_OK;
+}
+
+int lbm_batch_configure(lbm_batch* b, int rows, int store_mode, int order) {
+    if (!b) return LBM_ERR_ARG;
+    if (rows != 1 && rows != 2 && rows != 4) return bfail(b, LBM_ERR_ARG, "rows must be 1, 2 or 4");
+    if (store_mode != LBM_STORE_PLAIN && store_mode != LBM_STORE_NONTEMPORAL)
+        return bfail(b, LBM_ERR_ARG, "store mode must be PLAIN or NONTEMPORAL");
+    if (order < LBM_ORDER_GIVEN || order > LBM_ORDER_INTERLEAVED) return bfail(b, LBM_ERR_ARG, "unknown order");
+    return batch_apply(b, rows, store_mode == LBM_STORE_NONTEMPORAL, order);
 }
 
 }  // extern "C"

@@ -16,6 +16,10 @@ struct Launch {
     // the kernel of one time step (parity p; rows per tile 1, 2 or 4; nt selects
     // nontemporal stores)
     static void step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p, hipStream_t st);
+    // one time step of several simulations in one launch: workgroup b handles the tile
+    // sched[b] = (simulation, by << 16 | bx) of descs[simulation]
+    static void step_batch(const SimDesc* descs, const int2* sched, int nsched, int rows, bool nt,
+                           int p, hipStream_t st);
     static void fill(const SimDesc& d, const double g[NQ], int buf, hipStream_t st);
     static void set_pop(const SimDesc& d, const double* f, int buf, hipStream_t st);
     static void get_pop(const SimDesc& d, double* f, int buf, hipStream_t st);
@@ -25,8 +29,24 @@ struct Launch {
 // ---------------------------------------------------------------------------------
 // (A floor of 8 waves per SIMD forces spills into the body path and measured slower.)
 template <class S, int ROWS, bool NT>
-__global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ dp, int p) {
-    step_tile<S, ROWS, NT>(*dp, (int)blockIdx.x, (int)blockIdx.y, p);
+// One kernel serves a single simulation (sched == nullptr, 2D grid of its tiles) and a
+// batch (1D grid over sched).  The tile body has a single call site, so a simulation
+// computes bitwise the same inside a batch as alone.
+__global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ descs,
+                                                 const int2* __restrict__ sched, int p) {
+    const SimDesc* d;
+    int bx, by;
+    if (sched) {  // entry: (simulation, by << 16 | bx)
+        const int2 e = sched[blockIdx.x];
+        d = descs + e.x;
+        bx = e.y & 0xffff;
+        by = e.y >> 16;
+    } else {
+        d = descs;
+        bx = (int)blockIdx.x;
+        by = (int)blockIdx.y;
+    }
+    step_tile<S, ROWS, NT>(*d, bx, by, p);
 }
 
 __global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p);
@@ -109,11 +129,12 @@ __global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
 inline dim3 grid_rows(const SimDesc& d) { return dim3((d.nx + 255) / 256, d.ny); }
 
 template <class S, bool NT>
-static void launch_step_rows(const SimDesc* dd, dim3 grid, int rows, int p, hipStream_t st) {
+static void launch_step_rows(const SimDesc* dd, const int2* sched, dim3 grid, int rows, int p,
+                             hipStream_t st) {
     switch (rows) {
-        case 1: hipLaunchKernelGGL((k_step<S, 1, NT>), grid, dim3(TILE_X), 0, st, dd, p); break;
-        case 2: hipLaunchKernelGGL((k_step<S, 2, NT>), grid, dim3(TILE_X), 0, st, dd, p); break;
-        default: hipLaunchKernelGGL((k_step<S, 4, NT>), grid, dim3(TILE_X), 0, st, dd, p); break;
+        case 1: hipLaunchKernelGGL((k_step<S, 1, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p); break;
+        default: hipLaunchKernelGGL((k_step<S, 4, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p); break;
     }
 }
 
@@ -123,9 +144,17 @@ static void launch_step_rows(const SimDesc* dd, dim3 grid, int rows, int p, hipS
     void Launch<S>::step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p,            \
                          hipStream_t st) {                                                  \
         if (nt)                                                                             \
-            launch_step_rows<S, true>(dd, grid, rows, p, st);                               \
+            launch_step_rows<S, true>(dd, nullptr, grid, rows, p, st);                      \
         else                                                                                \
-            launch_step_rows<S, false>(dd, grid, rows, p, st);                              \
+            launch_step_rows<S, false>(dd, nullptr, grid, rows, p, st);                     \
+    }                                                                                       \
+    template <>                                                                             \
+    void Launch<S>::step_batch(const SimDesc* descs, const int2* sched, int nsched, int rows, \
+                               bool nt, int p, hipStream_t st) {                            \
+        if (nt)                                                                             \
+            launch_step_rows<S, true>(descs, sched, dim3(nsched), rows, p, st);             \
+        else                                                                                \
+            launch_step_rows<S, false>(descs, sched, dim3(nsched), rows, p, st);            \
     }                                                                                       \
     template <>                                                                             \
     void Launch<S>::fill(const SimDesc& d, const double g[NQ], int buf, hipStream_t st) {   \

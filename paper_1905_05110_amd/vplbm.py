@@ -19,12 +19,18 @@ LBM_OK, LBM_ERR_ARG, LBM_ERR_ALLOC, LBM_ERR_HIP, LBM_ERR_UNSTABLE, LBM_ERR_STATE
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 BC = {"periodic": 0, "wall": 1, "velocity": 2, "symmetry": 3, "outflow": 4}
 MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
+STORE = {"auto": 0, "plain": 1, "nontemporal": 2}
+ORDER = {"given": 0, "largest_first": 1, "interleaved": 2}
 
 EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
            "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
            "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
            "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_save", "lbm_load",
-           "lbm_destroy", "lbm_last_error"]
+           "lbm_destroy", "lbm_last_error",
+           "lbm_default_batch_opts", "lbm_batch_create", "lbm_batch_step",
+           "lbm_batch_set_graph_steps", "lbm_batch_sync", "lbm_batch_sim", "lbm_batch_size",
+           "lbm_batch_configure", "lbm_batch_autotune", "lbm_batch_destroy",
+           "lbm_batch_last_error"]
 
 
 class LbmError(RuntimeError):
@@ -55,6 +61,16 @@ class Body(C.Structure):
                 ("c", C.c_double * 3), ("q0", C.c_double * 3), ("f_ext", C.c_double * 3),
                 ("imp_amp", C.c_double), ("imp_freq", C.c_double), ("imp_y0", C.c_double),
                 ("smooth_delta", C.c_double), ("internal_mass_correction", C.c_int)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("rates", Rates), ("eta", C.c_double),
+                ("opts", C.POINTER(Opts)), ("body", C.POINTER(Body))]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("storage", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
+                ("order", C.c_int), ("hip_stream", C.c_void_p)]
 
 
 RECORD_DTYPE = np.dtype([("step", "<i8"), ("fvp", "<f8", (2,)), ("tvp", "<f8"),
@@ -99,6 +115,21 @@ def load_library(path=LIB_PATH):
     L.lbm_destroy.argtypes = [P]
     L.lbm_last_error.argtypes = [P]
     L.lbm_last_error.restype = C.c_char_p
+    L.lbm_default_batch_opts.argtypes = [C.POINTER(BatchOpts)]
+    L.lbm_default_batch_opts.restype = None
+    L.lbm_batch_create.argtypes = [C.c_int, C.POINTER(BatchDesc), C.POINTER(BatchOpts),
+                                   C.POINTER(P)]
+    L.lbm_batch_step.argtypes = [P, C.c_int64]
+    L.lbm_batch_set_graph_steps.argtypes = [P, C.c_int]
+    L.lbm_batch_sync.argtypes = [P]
+    L.lbm_batch_sim.argtypes = [P, C.c_int, C.POINTER(P)]
+    L.lbm_batch_size.argtypes = [P]
+    L.lbm_batch_configure.argtypes = [P, C.c_int, C.c_int, C.c_int]
+    L.lbm_batch_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.lbm_batch_destroy.argtypes = [P]
+    L.lbm_batch_last_error.argtypes = [P]
+    L.lbm_batch_last_error.restype = C.c_char_p
     _LIB = L
     return L
 
@@ -167,8 +198,19 @@ class Sim:
     library allocates its own buffers and stream.
     """
 
+    @classmethod
+    def _member(cls, L, h, spec):
+        """Borrowed handle of a batch member (the batch owns and frees it)."""
+        self = cls.__new__(cls)
+        self.L, self.h, self.spec = L, h, dict(spec)
+        self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
+        self._tensors = None
+        self._borrowed = True
+        return self
+
     def __init__(self, spec, body=None, torch_memory=False, history_cap=65536, graph_steps=0):
         L = load_library()
+        self._borrowed = False
         self.L = L
         self.spec = dict(spec)
         self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
@@ -274,9 +316,105 @@ class Sim:
 
     def close(self):
         if getattr(self, "h", None):
-            self.L.lbm_destroy(self.h)
+            if not getattr(self, "_borrowed", False):
+                self.L.lbm_destroy(self.h)
             self.h = None
         self._tensors = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many independent simulations advanced by one kernel launch per step.
+
+    ``members`` is a list of (spec, body-or-None); all share ``storage`` and the launch
+    configuration.  ``batch.sims[i]`` is a borrowed :class:`Sim` for reading member i
+    (forces, fields, body state, populations); stepping goes through the batch.
+    """
+
+    def __init__(self, members, storage="fp32", order="largest_first", rows=0, store="auto",
+                 history_cap=65536, graph_steps=0, stream=None):
+        L = load_library()
+        self.L = L
+        self.h = None
+        n = len(members)
+        self._opts = (Opts * n)()
+        self._bodies = (Body * n)()
+        descs = (BatchDesc * n)()
+        for i, (spec, body) in enumerate(members):
+            self._opts[i] = make_opts(dict(spec, storage=storage), None, None, history_cap)
+            descs[i].nx, descs[i].ny = int(spec["nx"]), int(spec["ny"])
+            descs[i].rates = Rates(*[float(x) for x in spec["rates"]])
+            descs[i].eta = float(spec["eta"])
+            descs[i].opts = C.pointer(self._opts[i])
+            if body is not None:
+                self._bodies[i] = make_body(body)
+                descs[i].body = C.pointer(self._bodies[i])
+        bo = BatchOpts()
+        L.lbm_default_batch_opts(C.byref(bo))
+        bo.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        bo.order = ORDER[order] if isinstance(order, str) else int(order)
+        bo.rows_per_tile = int(rows)
+        bo.store_mode = STORE[store] if isinstance(store, str) else int(store)
+        bo.hip_stream = stream
+        h = C.c_void_p()
+        rc = L.lbm_batch_create(n, descs, C.byref(bo), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError(rc, L.lbm_batch_last_error(None).decode())
+        self.h = h
+        self.sims = []
+        for i, (spec, _) in enumerate(members):
+            sh = C.c_void_p()
+            self._check(L.lbm_batch_sim(self.h, i, C.byref(sh)))
+            self.sims.append(Sim._member(L, sh, dict(spec, storage=storage)))
+        if graph_steps:
+            self.set_graph_steps(graph_steps)
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.L.lbm_batch_last_error(self.h).decode())
+        return rc
+
+    def __len__(self):
+        return len(self.sims)
+
+    def step(self, n=1):
+        self._check(self.L.lbm_batch_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.L.lbm_batch_sync(self.h))
+
+    def set_graph_steps(self, k):
+        self._check(self.L.lbm_batch_set_graph_steps(self.h, int(k)))
+
+    def configure(self, rows, store, order):
+        self._check(self.L.lbm_batch_configure(
+            self.h, int(rows), STORE[store] if isinstance(store, str) else int(store),
+            ORDER[order] if isinstance(order, str) else int(order)))
+
+    def autotune(self, trial_steps=20):
+        """Pick rows, store mode and order by timing; returns (rows, nt, order, us/step)."""
+        r, n, o, us = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        self._check(self.L.lbm_batch_autotune(self.h, int(trial_steps), C.byref(r), C.byref(n),
+                                              C.byref(o), C.byref(us)))
+        return r.value, n.value, o.value, us.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in self.sims:
+                s.h = None
+            self.L.lbm_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

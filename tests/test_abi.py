@@ -83,3 +83,56 @@ def test_create_without_device_reports_hip_error(lib):
     rc, h, msg = _create(lib)
     assert rc == vplbm.LBM_ERR_HIP
     assert msg
+
+
+def _batch_desc(nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3):
+    d = vplbm.BatchDesc()
+    d.nx, d.ny = nx, ny
+    d.rates = vplbm.Rates(*rates)
+    d.eta = eta
+    return d
+
+
+@pytest.mark.parametrize("field,value,frag", [
+    ("order", 3, "order"),
+    ("store_mode", 5, "store mode"),
+    ("storage", 9, "storage"),
+    ("rows_per_tile", 3, "rows_per_tile"),
+])
+def test_invalid_batch_options_are_rejected(lib, field, value, frag):
+    descs = (vplbm.BatchDesc * 2)(_batch_desc(), _batch_desc(12, 9))
+    bo = vplbm.BatchOpts()
+    lib.lbm_default_batch_opts(C.byref(bo))
+    setattr(bo, field, value)
+    h = C.c_void_p()
+    assert lib.lbm_batch_create(2, descs, C.byref(bo), C.byref(h)) == vplbm.LBM_ERR_ARG
+    assert frag in lib.lbm_batch_last_error(None).decode()
+    assert not h.value
+
+
+def test_batch_null_arguments_are_rejected(lib):
+    h = C.c_void_p()
+    descs = (vplbm.BatchDesc * 1)(_batch_desc())
+    assert lib.lbm_batch_create(0, descs, None, C.byref(h)) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_batch_create(1, None, None, C.byref(h)) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_batch_step(None, 1) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_batch_sync(None) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_batch_destroy(None) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_batch_size(None) == -1
+    assert lib.lbm_batch_sim(None, 0, C.byref(h)) == vplbm.LBM_ERR_ARG
+
+
+def test_batch_struct_layout(lib):
+    assert C.sizeof(vplbm.BatchOpts) == 4 * 4 + 8
+    assert C.sizeof(vplbm.BatchDesc) == 4 * 2 + 8 * 4 + 8 + 8 + 8
+
+
+def test_batch_create_without_device_reports_hip_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    descs = (vplbm.BatchDesc * 2)(_batch_desc(), _batch_desc(12, 9))
+    h = C.c_void_p()
+    assert lib.lbm_batch_create(2, descs, None, C.byref(h)) == vplbm.LBM_ERR_HIP
+    assert lib.lbm_batch_last_error(None).decode()
+    assert not h.value

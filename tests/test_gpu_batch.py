@@ -1,0 +1,164 @@
+"""Batches of independent simulations (one launch per step over all their tiles).
+
+A member of a batch runs the same kernel, from the same call site, as a simulation on
+its own in the same launch configuration, so each member must be bitwise equal to its
+standalone run; FP64 members are also compared with the FP64 CPU oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1905_05110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05110_amd import vplbm
+    vplbm.load_library()
+    return vplbm
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def mixed_members(storage):
+    """Five grids of different sizes, boundaries and body kinds (one without a body);
+    sizes span one to several tiles and ragged tails."""
+    out = []
+    wl = W.imposed_oscillation(storage=storage, nx=300, ny=70, D=16.0)
+    out.append((wl["spec"], wl["body"]))
+    wl = W.free_viv(storage=storage, nx=520, ny=130, D=20.0)
+    out.append((wl["spec"], wl["body"]))
+    spec = dict(nx=97, ny=45, rates=(1.64, 1.54, 1.9, 1.25), eta=1e-3,
+                bc=("wall",) * 4, u_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [0.04, 0.0]],
+                u_conv=0.0, g_fluid=(1e-6, 0.0), rho0=1.0, u0=(0.0, 0.0), storage=storage)
+    out.append((spec, None))
+    spec = dict(nx=64, ny=260, rates=(1.64, 1.54, 1.9, 1.1), eta=1e-3, bc=("wall",) * 4,
+                u_wall=[[0.0, 0.0]] * 4, u_conv=0.0, g_fluid=(0.0, 0.0), rho0=1.0,
+                u0=(0.0, 0.0), storage=storage)
+    b = W.fixed_disc(12.0, 31.7, 200.4)
+    b.update(mode="free", free_mask=7, mass=300.0, inertia=4000.0,
+             f_ext=(0.0, -0.02, 0.0))
+    out.append((spec, b))
+    wl = W.imposed_oscillation(storage=storage, nx=257, ny=33, D=10.0)
+    wl["body"].update(smooth_delta=1.0)
+    out.append((wl["spec"], wl["body"]))
+    return out
+
+
+@pytest.mark.parametrize("storage,rows,store", [("fp64", 1, "plain"), ("fp32", 2, "plain"),
+                                                ("fp16", 4, "nontemporal"),
+                                                ("bf16", 2, "nontemporal")])
+def test_members_are_bitwise_equal_to_standalone_runs(gpu, storage, rows, store):
+    _flush("batch vs standalone %s rows %d %s" % (storage, rows, store))
+    members = mixed_members(storage)
+    batch = gpu.Batch(members, storage=storage, rows=rows, store=store, graph_steps=8)
+    batch.step(3)
+    batch.step(30)
+    batch.sync()
+    for i, (spec, body) in enumerate(members):
+        s = gpu.Sim(dict(spec, rows_per_tile=rows, store_mode=store), body)
+        s.step(33)
+        s.sync()
+        m = batch.sims[i]
+        assert m.step_index() == 33
+        assert np.array_equal(m.get_populations(), s.get_populations()), i
+        if body is not None:
+            rm, rs = m.forces(), s.forces()
+            assert len(rm) == 33
+            for key in ("fvp", "tvp", "pin", "fh", "th", "q", "v"):
+                assert np.array_equal(rm[key], rs[key]), (i, key)
+        s.close()
+    batch.close()
+
+
+@pytest.mark.parametrize("order", ["given", "largest_first", "interleaved"])
+def test_schedule_order_does_not_change_results(gpu, order):
+    members = mixed_members("fp32")
+    ref = gpu.Batch(members, storage="fp32", rows=1, store="plain", order="given")
+    ref.step(20)
+    b = gpu.Batch(members, storage="fp32", rows=1, store="plain", order=order)
+    b.step(20)
+    for i in range(len(members)):
+        assert np.array_equal(b.sims[i].get_populations(), ref.sims[i].get_populations())
+    ref.close()
+    b.close()
+
+
+def test_fp64_members_match_the_oracle(gpu):
+    from oracle import oracle as orc
+    members = mixed_members("fp64")
+    batch = gpu.Batch(members, storage="fp64", rows=1, store="plain")
+    batch.step(25)
+    for i in (0, 2, 4):
+        spec, body = members[i]
+        _flush("batch member %d vs oracle (%dx%d)" % (i, spec["nx"], spec["ny"]))
+        o = orc.OracleSim(spec, body)
+        ro = o.step(25)
+        m = batch.sims[i]
+        assert rel(m.get_populations(), o.get_populations()) <= 1e-12
+        if body is not None:
+            rm = m.forces()
+            assert rel(rm["fvp"], ro["fvp"]) <= 1e-11
+            assert np.abs(rm["q"] - ro["q"]).max() <= 1e-10
+    batch.close()
+
+
+def test_members_refuse_standalone_stepping(gpu):
+    members = mixed_members("fp32")[:2]
+    batch = gpu.Batch(members, storage="fp32")
+    m = batch.sims[0]
+    for call in (lambda: m.step(1), lambda: m.set_graph_steps(4),
+                 lambda: m.autotune(trial_steps=1), lambda: m.load(np.zeros(64, np.uint8))):
+        with pytest.raises(gpu.LbmError) as e:
+            call()
+        assert e.value.code == gpu.LBM_ERR_STATE
+    assert gpu.load_library().lbm_destroy(m.h) == gpu.LBM_ERR_STATE
+    batch.step(4)
+    batch.sync()
+    assert m.step_index() == 4
+    batch.close()
+
+
+def test_member_body_can_be_replaced(gpu):
+    """set_body on a member changes that member only; the batch keeps stepping."""
+    members = mixed_members("fp32")[:3]
+    batch = gpu.Batch(members, storage="fp32", rows=1, store="plain")
+    batch.step(6)
+    assert len(batch.sims[2].forces()) == 0  # no body: no records
+    spec, body = members[2]
+    b = W.fixed_disc(10.0, 40.3, 22.1)
+    batch.sims[2].set_body(b)
+    batch.step(10)
+    batch.sync()
+    r = batch.sims[2].forces()
+    assert len(r) == 10 and np.isfinite(r["fvp"]).all() and np.abs(r["fvp"]).max() > 0
+    batch.close()
+
+
+def test_batch_autotune_and_sweep(gpu):
+    """The 64-run sweep of uneven VIV grids: autotune, then steps with no instability."""
+    sweep = W.batch_sweep(storage="fp32")
+    members = [(w["spec"], w["body"]) for w in sweep]
+    _flush("batch sweep of %d grids, %d nodes" % (len(members),
+                                                   sum(s["nx"] * s["ny"] for s, _ in members)))
+    batch = gpu.Batch(members, storage="fp32", graph_steps=16, history_cap=256)
+    rows, nt, order, us = batch.autotune(trial_steps=8)
+    assert rows in (1, 2, 4) and nt in (0, 1) and order in (0, 1, 2) and us > 0
+    batch.step(64)
+    batch.sync()
+    q, v = batch.sims[17].body_state()
+    assert np.isfinite(q).all() and np.isfinite(v).all()
+    batch.close()

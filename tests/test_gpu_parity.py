@@ -106,7 +106,10 @@ def run_pair(gpu, spec, body, steps, seed, check_every=1, tol=1e-12, init_random
         e = rel(fg, fo)
         worst = max(worst, e)
         assert e <= tol, (s, e)
-        fe = force_err(rg, ro, body["radius"] if body else 0.0)
+        if body is None:
+            assert len(rg) == 0  # steps without a body have no record
+            continue
+        fe = force_err(rg, ro, body["radius"])
         for key in ("fvp", "tvp", "pin", "fh", "th"):
             if np.abs(ro[key]).max() > 1e-14:
                 assert fe[key] <= tol * 10, (s, key, fe)
@@ -375,3 +378,20 @@ def test_autotune_applies_a_configuration(gpu, tmp_path):
     assert np.array_equal(a.get_populations(), b.get_populations())
     a.close()
     b.close()
+
+
+def test_records_exist_only_for_steps_with_a_body(gpu):
+    wl = W.imposed_oscillation(storage="fp32", nx=120, ny=48, D=12.0)
+    g = gpu.Sim(wl["spec"], wl["body"])
+    g.step(3)
+    g.clear_body()
+    g.step(4)
+    r = g.forces()
+    assert list(r["step"]) == [0, 1, 2]
+    g.step(2)
+    assert len(g.forces()) == 0
+    g.set_body(wl["body"])
+    g.step(2)
+    r = g.forces()
+    assert list(r["step"]) == [9, 10] and np.isfinite(r["fvp"]).all()
+    g.close()
