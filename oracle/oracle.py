@@ -46,6 +46,7 @@ class Params(C.Structure):
         ("f_ext", C.c_double * 3),
         ("imp_amp", C.c_double), ("imp_freq", C.c_double), ("imp_y0", C.c_double),
         ("internal_mass_correction", C.c_int),
+        ("chi_add", C.c_void_p),
     ]
 
 
@@ -195,10 +196,22 @@ class OracleSim:
 
     def set_body(self, body):
         self.p = make_params(self.spec, body, self.conserved)
+        self._apply_chi_add()
         q = np.array([body["x"], body["y"], body.get("theta", 0.0)], dtype=np.float64)
         v = np.array([body.get("vx", 0.0), body.get("vy", 0.0), body.get("omega", 0.0)],
                      dtype=np.float64)
         lib().orc_body_init(C.byref(self.p), C.byref(self.b), q, v)
+
+    def set_chi_perturbation(self, field):
+        """Field [ny, nx] added to the indicator of the body at every step (None: off)."""
+        self._chi_add = None if field is None else np.ascontiguousarray(field, dtype=np.float64)
+        if self._chi_add is not None:
+            assert self._chi_add.shape == (self.ny, self.nx)
+        self._apply_chi_add()
+
+    def _apply_chi_add(self):
+        ca = getattr(self, "_chi_add", None)
+        self.p.chi_add = None if ca is None else ca.ctypes.data
 
     def set_populations(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64)

@@ -72,6 +72,9 @@ typedef struct {
     double k[3], c[3], q0[3], f_ext[3];
     double imp_amp, imp_freq, imp_y0;
     int internal_mass_correction;
+    /* optional [ny][nx] field added to the indicator (NULL: none); the design variable
+     * of the sensitivity checks, perturbed node by node for finite differences */
+    const double* chi_add;
 } orc_params;
 
 typedef struct {
@@ -167,6 +170,7 @@ void orc_chi(const orc_params* p, const orc_body* b, int i, int j, double* chi, 
         else
             *chi = 1.0 / (1.0 + exp(2.0 * z));
     }
+    if (p->chi_add) *chi += p->chi_add[(size_t)j * (size_t)p->nx + (size_t)i];
     /* rigid motion: u_s = V + Omega e_z x (x - x_G) */
     *usx = b->v[0] - b->v[2] * dy;
     *usy = b->v[1] + b->v[2] * dx;
