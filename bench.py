@@ -17,6 +17,12 @@ all advanced by one launch per step.  ``--accuracy-steps N`` then also runs the 
 for N steps in every storage precision and reports, per precision, the relative error
 of each run's mean drag coefficient and RMS lift coefficient over the second half of
 the run against the FP64 runs.
+
+``--workload adjoint`` times the reverse-mode path: gradient of the time-averaged drag
+coefficient of a fixed disc (D = 32, Re = 100, tanh indicator, 1024x512 channel) over
+4000 steps with a checkpoint every 100, with respect to the indicator field and the
+disc centre.  The value is the adjoint/forward time ratio (backward sweep including
+the recomputation, over the forward run including the checkpoint copies).
 """
 import argparse
 import json
@@ -34,7 +40,7 @@ BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}  # 9 reads + 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="free_viv", choices=("free_viv", "batch_sweep"))
+    ap.add_argument("--workload", default="free_viv", choices=("free_viv", "batch_sweep", "adjoint"))
     ap.add_argument("--accuracy-steps", type=int, default=0,
                     help="batch_sweep: also compare storages over this many steps")
     ap.add_argument("--steps", type=int, default=20000)
@@ -234,6 +240,86 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_baseline_adjoint(target_seconds):
+    """Reverse-mode oracle (torch-CPU FP64) on the 128x64 copy of the workload."""
+    import torch
+    from oracle import adjoint_oracle as ado
+    from paper_1905_05110_amd import workloads as W
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    torch.set_num_threads(cores)
+    wl = W.adjoint_drag(storage="fp64", nx=128, ny=64, D=8.0)
+    m = ado.Mirror(wl["spec"], wl["body"])
+    t0 = time.perf_counter()
+    m.gradient(100, 50, (1.0, 0.0))
+    per_step = (time.perf_counter() - t0) / 100
+    n = max(100, min(2000, int(target_seconds / per_step) // 100 * 100))
+    t0 = time.perf_counter()
+    m.gradient(n, 100, (1.0, 0.0))
+    dt = time.perf_counter() - t0
+    return {"value": round(128 * 64 * n / dt / 1e6, 3), "unit": "MLUPS (forward + reverse)",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "reverse-mode oracle, 128x64 copy, %d steps (%.1f s)" % (n, dt)}
+
+
+def run_adjoint(args):
+    import statistics
+    from paper_1905_05110_amd import workloads as W
+    from paper_1905_05110_amd import vplbm
+
+    wl = W.adjoint_drag(storage=args.storage)
+    steps, every = wl["steps"], wl["checkpoint_every"]
+    w = (1.0 / (steps * 0.5 * wl["U0"] ** 2 * wl["D"]), 0.0)
+    nodes = wl["spec"]["nx"] * wl["spec"]["ny"]
+    adj = vplbm.Adjoint(wl["spec"], wl["body"], steps, every, w)
+    print("adjoint warm-up", file=sys.stderr, flush=True)
+    J = adj.forward()
+    adj.backward()
+    tf, tb = [], []
+    for rep in range(3):
+        t0 = time.perf_counter()
+        adj.forward()
+        t1 = time.perf_counter()
+        adj.backward()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+        print("rep %d forward %.4f s backward %.4f s" % (rep, tf[-1], tb[-1]), file=sys.stderr,
+              flush=True)
+    g = adj.gradient(chi=False)
+    fwd, bwd = statistics.median(tf), statistics.median(tb)
+    adj_us, step_us = adj.time_kernels(reps=400)
+    esize = {"fp32": 4, "fp64": 8}[args.storage]
+    # adjoint step per node: 9 state reads (re-pull), 9 adjoint reads, 9 adjoint writes,
+    # dJ/dchi read and write
+    adj_bytes = nodes * 29 * esize
+    achieved = adj_bytes / (adj_us * 1e-6) / 1e9
+    out = {
+        "metric": "adjoint/forward time ratio (gradient of time-averaged drag)",
+        "value": round(bwd / fwd, 3), "unit": "ratio", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": round(1e3 * (fwd + bwd) / steps, 5), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64"}[args.storage],
+        "data": "synthetic (channel flow from a uniform inflow state; no dataset)",
+        "config": {"workload": "adjoint_drag_1024x512", "nx": wl["spec"]["nx"],
+                   "ny": wl["spec"]["ny"], "storage": args.storage, "D": wl["D"], "Re": 100,
+                   "steps": steps, "checkpoint_every": every, "indicator": "tanh, delta = 1"},
+        "forward_s": round(fwd, 5), "backward_s": round(bwd, 5),
+        "forward_mlups": round(nodes * steps / fwd / 1e6, 1),
+        "backward_mlups": round(nodes * steps / bwd / 1e6, 1),
+        "J": J, "dJ_dpos": [float(x) for x in g["pos"]],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_adjoint<%s>" % args.storage, "avg_kernel_us": round(adj_us, 3),
+                     "algorithmic_bytes_per_launch": adj_bytes,
+                     "forward_step_kernel_us": round(step_us, 3)},
+    }
+    adj.close()
+    if not args.no_cpu_baseline:
+        print("cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_adjoint(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,6 +328,11 @@ def main():
         sys.exit(2)
     if args.workload == "batch_sweep":
         return run_batch(args)
+    if args.workload == "adjoint":
+        if args.storage not in ("fp32", "fp64"):
+            print("the adjoint runs in fp32 or fp64 storage", file=sys.stderr)
+            sys.exit(2)
+        return run_adjoint(args)
     import torch
     from paper_1905_05110_amd import workloads as W
     from paper_1905_05110_amd import vplbm

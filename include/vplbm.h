@@ -290,6 +290,65 @@ int lbm_batch_autotune(lbm_batch* batch, int trial_steps, int* rows_out, int* nt
 int lbm_batch_destroy(lbm_batch* batch);
 const char* lbm_batch_last_error(const lbm_batch* batch);
 
+/* ---- adjoint: gradients of the time-integrated penalization force --------------------
+ * For a body held at a fixed pose with rigid velocity (V, Omega) (lbm_body with mode
+ * LBM_BODY_FIXED), the objective
+ *     J = sum_{n < N} ( w_x F_vp,x(n) + w_y F_vp,y(n) )
+ * (F_vp the penalization force of step n, lbm_force_rec.fvp; w = 1 / (N rho0 U0^2 D / 2)
+ * makes J the time-averaged drag coefficient) is differentiated in reverse mode through
+ * the N steps (Sec. 2.2 step, Sec. 2.1 indicator): dJ/dchi at every node (the indicator
+ * taken as a free field), dJ/d(X, Y) (through the smoothed indicator of lbm_body
+ * smooth_delta > 0 and through u_s; a sharp indicator contributes through u_s only) and
+ * dJ/d(V_x, V_y, Omega).  The forward run keeps a checkpoint every K steps; the backward
+ * run recomputes each segment of K steps from its checkpoint and sweeps it in reverse.
+ * Device memory: about (N/K + K + 8) population buffers (lbm_pop_bytes).
+ * FP64 and FP32 storage (arithmetic in the storage precision). */
+typedef struct lbm_adjoint lbm_adjoint;
+
+typedef struct {
+    int64_t steps;         /* N >= 1, a multiple of checkpoint_every */
+    int checkpoint_every;  /* K >= 2, even */
+    double weight_fx;      /* w_x */
+    double weight_fy;      /* w_y */
+} lbm_adjoint_opts;
+
+void lbm_default_adjoint_opts(lbm_adjoint_opts* o);  /* N = 4000, K = 100, w = (1, 0) */
+
+/* Creates the simulation (arguments as lbm_create and lbm_set_body; opts may be NULL)
+ * and the adjoint buffers.  The initial state is the uniform equilibrium (rho0, u0). */
+int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts,
+                       const lbm_body* body, const lbm_adjoint_opts* aopts, lbm_adjoint** out);
+
+/* Moves the body (mode FIXED); the next forward run starts again from the initial state. */
+int lbm_adjoint_set_body(lbm_adjoint* adj, const lbm_body* body);
+
+/* Initial state of the forward run: post-collision populations [9][ny][nx] and the
+ * outflow memory [3][ny] (directions 3, 6, 7), FP64 host arrays; NULL restores the
+ * uniform equilibrium for that part. */
+int lbm_adjoint_set_initial(lbm_adjoint* adj, const double* f, const double* outlet);
+
+/* Runs the N forward steps from the initial state, keeping the checkpoints; *J receives
+ * the objective (FP64 sum of the per-step records in step order).  Synchronous. */
+int lbm_adjoint_forward(lbm_adjoint* adj, double* J);
+
+/* Records of the last forward run (up to cap, oldest first). */
+int lbm_adjoint_forces(lbm_adjoint* adj, lbm_force_rec* out, int64_t cap, int64_t* n_out);
+
+/* Reverse sweep over the last forward run.  Synchronous.  LBM_ERR_STATE without one. */
+int lbm_adjoint_backward(lbm_adjoint* adj);
+
+/* Gradients of the last backward run: dJ_dchi [ny][nx] (may be NULL), dJ_dpos (X, Y),
+ * dJ_dvel (V_x, V_y, Omega); FP64 host arrays. */
+int lbm_adjoint_gradient(lbm_adjoint* adj, double* dJ_dchi, double* dJ_dpos, double* dJ_dvel);
+
+/* Measurement: average duration (microseconds, HIP events) of reps launches of the
+ * adjoint step kernel and of the forward step kernel on the segment store.  Overwrites
+ * the accumulators: run lbm_adjoint_backward again before reading gradients. */
+int lbm_adjoint_time_kernels(lbm_adjoint* adj, int reps, double* adjoint_us, double* step_us);
+
+int lbm_adjoint_destroy(lbm_adjoint* adj);
+const char* lbm_adjoint_last_error(const lbm_adjoint* adj);
+
 /* Frees everything the library allocated for the simulation. */
 int lbm_destroy(lbm_sim* sim);
 

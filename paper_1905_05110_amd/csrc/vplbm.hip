@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "vplbm.h"
+#include "vplbm_host.hpp"
 #include "vplbm_kernels.hpp"
 
 using namespace vplbm;
@@ -29,89 +30,8 @@ __global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__
 // host runtime
 // ---------------------------------------------------------------------------------
 namespace {
-
 thread_local std::string g_create_error;
-
-size_t elem_size(int storage) {
-    switch (storage) {
-        case LBM_FP64: return 8;
-        case LBM_FP32: return 4;
-        default: return 2;
-    }
-}
-
-int row_pitch(int nx) { return (nx + 63) / 64 * 64; }
-
-long long plane_stride(int nx, int ny) {
-    // pad planes by 5 x 64 elements so the nine streams do not start on the same
-    // large power-of-two boundary
-    return (long long)row_pitch(nx) * ny + 320;
-}
-
 }  // namespace
-
-struct lbm_sim {
-    int nx = 0, ny = 0, storage = LBM_FP32;
-    size_t pop_bytes = 0;
-    void* pop[2] = {nullptr, nullptr};
-    bool own_pop = false;
-    void* outlet = nullptr;
-    BodyDev* body_d = nullptr;
-    double* partials = nullptr;
-    Record* hist = nullptr;
-    int* flag = nullptr;
-    double* staging = nullptr;  // FP64 [9][ny][nx] for set/get/fields
-    SimDesc desc{};
-    SimDesc* desc_d = nullptr;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int64_t host_step = 0;
-    int64_t drained = 0;
-    int64_t rec_end = 0;  // without a body: records exist for the steps before this one
-    int hist_cap = 65536;
-    lbm_opts opts{};
-    lbm_rates rates{};
-    double eta = 0.0;
-    BodyDev body_h{};
-    lbm_body body_desc{};  // last body set (used by the autotuner)
-    bool has_body = false;
-    std::string err;
-    int graph_steps = 0;
-    int rows = 1;   // rows of a tile (nodes per lane)
-    bool nt = false;  // nontemporal population stores
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    bool in_batch = false;  // member of an lbm_batch: stepped, configured and freed by it
-};
-
-#define HIP_TRY(sim, expr)                                                             \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess) {                                                        \
-            (sim)->err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
-            return LBM_ERR_HIP;                                                        \
-        }                                                                              \
-    } while (0)
-
-static int fail(lbm_sim* s, int code, const std::string& msg) {
-    if (s) s->err = msg;
-    return code;
-}
-
-static int reject_member(lbm_sim* s) {
-    return fail(s, LBM_ERR_STATE, "a member of a batch is stepped, configured and freed by its batch");
-}
-
-
-template <class F>
-static int dispatch(int storage, F&& f) {
-    switch (storage) {
-        case LBM_FP64: return f((double*)nullptr);
-        case LBM_FP32: return f((float*)nullptr);
-        case LBM_FP16_OFS: return f((_Float16*)nullptr);
-        default: return f((bf16s*)nullptr);
-    }
-}
 
 static const double kW[NQ] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                               1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
@@ -145,7 +65,7 @@ static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nu
     if (ev0) HIP_TRY(s, hipEventRecord(ev0, s->stream));
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, p, s->stream);
+        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, p, s->stream, s->row_shift);
         return LBM_OK;
     });
     if (ev1) HIP_TRY(s, hipEventRecord(ev1, s->stream));
@@ -306,6 +226,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.pop[0] = s->pop[0];
     d.pop[1] = s->pop[1];
     d.outlet = s->outlet;
+    d.outlet_out = s->outlet;
     d.body = s->body_d;
     d.partials = s->partials;
     d.part_stride = (long long)ntiles * NRED;
@@ -484,6 +405,10 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     st.fresh = 1;
     body_tiles(s->nx, s->ny, s->rows, B, q[0], q[1], st.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
+    if (s->row_shift != st.boxM[2]) {  // captured launches carry the row shift
+        s->row_shift = st.boxM[2];
+        drop_graph(s);
+    }
     s->body_h = B;
     s->body_desc = *b;
     if (!s->has_body) s->drained = std::max(s->drained, s->host_step);  // body-less steps
@@ -504,6 +429,10 @@ int lbm_clear_body(lbm_sim* s) {
     st.pin_valid = 0;
     st.fresh = 1;
     for (int k = 0; k < 4; ++k) st.boxM[k] = st.part_box[k] = 0;
+    if (s->row_shift != 0) {
+        s->row_shift = 0;
+        drop_graph(s);
+    }
     if (s->has_body) s->rec_end = s->host_step;
     s->has_body = false;
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
@@ -688,6 +617,7 @@ static int apply_launch_config(lbm_sim* s, int rows, bool nt) {
     BodyState& st = B.st[s->host_step & 1];
     body_tiles(s->nx, s->ny, rows, B, st.q[0], st.q[1], st.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
+    s->row_shift = st.boxM[2];
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     int rc = upload_desc(s);
     if (rc) return rc;
@@ -855,6 +785,7 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     BodyDev B;
     std::memcpy(&B, c, sizeof(B));
     s->has_body = B.active != 0;
+    s->row_shift = std::min(std::max(B.st[s->host_step & 1].boxM[2], 0), s->desc.tiles_y - 1);
     if (!s->has_body) s->rec_end = s->drained = std::max(s->drained, s->host_step);
     HIP_TRY(s, hipMemset(s->flag, 0, sizeof(int)));
     drop_graph(s);
@@ -935,8 +866,10 @@ static std::vector<int2> batch_schedule(const lbm_batch* b, int order) {
     }
     for (int i : idx) {
         const SimDesc& d = b->sims[i]->desc;
-        for (int r = 0; r < d.tiles_y; ++r)
+        for (int r0 = 0; r0 < d.tiles_y; ++r0) {
+            const int r = (r0 + b->sims[i]->row_shift) % d.tiles_y;  // body rows first
             for (int x = 0; x < d.tiles_x; ++x) out.push_back(make_int2(i, (r << 16) | x));
+        }
     }
     return out;
 }

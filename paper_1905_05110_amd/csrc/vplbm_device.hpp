@@ -109,6 +109,7 @@ struct Consts {
 struct SimDesc {
     void* pop[2];        // two population buffers, 9 planes of ps elements each
     void* outlet;        // 3 x ny offsets (directions 3, 6, 7) of the outflow memory
+    void* outlet_out;    // where the step writes the next memory (normally == outlet)
     BodyDev* body;
     double* partials;    // NRED FP64 sums per participating tile, two parities
     long long part_stride;  // doubles per parity in partials
@@ -143,15 +144,27 @@ struct bf16s {
 template <class S>
 struct Codec;
 
+// Population buffers live in global memory: accesses through these address-space-1
+// pointers compile to global loads and stores with a uniform (scalar) base and a
+// 32-bit lane offset, instead of flat accesses with 64-bit lane addresses.
+typedef __attribute__((address_space(1))) const double g_cdouble;
+typedef __attribute__((address_space(1))) double g_double;
+typedef __attribute__((address_space(1))) const float g_cfloat;
+typedef __attribute__((address_space(1))) float g_float;
+typedef __attribute__((address_space(1))) const _Float16 g_chalf;
+typedef __attribute__((address_space(1))) _Float16 g_half;
+typedef __attribute__((address_space(1))) const uint16_t g_cu16;
+typedef __attribute__((address_space(1))) uint16_t g_u16;
+
 template <>
 struct Codec<double> {
     using T = double;
     static __device__ __forceinline__ T load(const char* base, unsigned off, float) {
-        return *reinterpret_cast<const double*>(base + off);
+        return *(g_cdouble*)(base + off);
     }
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float) {
-        double* q = reinterpret_cast<double*>(base + off);
+        g_double* q = (g_double*)(base + off);
         if (NT) __builtin_nontemporal_store(v, q); else *q = v;
     }
 };
@@ -160,11 +173,11 @@ template <>
 struct Codec<float> {
     using T = float;
     static __device__ __forceinline__ T load(const char* base, unsigned off, float) {
-        return *reinterpret_cast<const float*>(base + off);
+        return *(g_cfloat*)(base + off);
     }
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float) {
-        float* q = reinterpret_cast<float*>(base + off);
+        g_float* q = (g_float*)(base + off);
         if (NT) __builtin_nontemporal_store(v, q); else *q = v;
     }
 };
@@ -174,11 +187,11 @@ struct Codec<_Float16> {
     using T = float;
     // stored value: round-to-nearest-even of g * 2^k
     static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
-        return (float)*reinterpret_cast<const _Float16*>(base + off) * inv_scale;
+        return (float)*(g_chalf*)(base + off) * inv_scale;
     }
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
-        _Float16* q = reinterpret_cast<_Float16*>(base + off);
+        g_half* q = (g_half*)(base + off);
         const _Float16 h = (_Float16)(v * scale);
         if (NT) __builtin_nontemporal_store(h, q); else *q = h;
     }
@@ -195,16 +208,26 @@ template <>
 struct Codec<bf16s> {
     using T = float;
     static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
-        const uint16_t b = *reinterpret_cast<const uint16_t*>(base + off);
+        const uint16_t b = *(g_cu16*)(base + off);
         return __builtin_bit_cast(float, (uint32_t)b << 16) * inv_scale;
     }
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
-        uint16_t* q = reinterpret_cast<uint16_t*>(base + off);
+        g_u16* q = (g_u16*)(base + off);
         const uint16_t b = f32_to_bf16_rne(v * scale);
         if (NT) __builtin_nontemporal_store(b, q); else *q = b;
     }
 };
+
+// Global-memory load and store of a T through an address-space-1 pointer.
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
 
 template <class S>
 __device__ __forceinline__ unsigned node_off(const SimDesc& d, int i, int j) {
@@ -265,31 +288,118 @@ __device__ bool pull_rules(const SimDesc& d, const void* fin, int a, int i, int 
 // Index of a direction in the 3-slot outflow memory (directions 3, 6, 7).
 __device__ __forceinline__ int outflow_slot(int a) { return a == 3 ? 0 : (a == 6 ? 1 : 2); }
 
-// Pulled offsets of a node on the domain edge, through the boundary rules.  When
-// update_outlet is set, the east column stores its pulled values 3, 6, 7 as the
-// outflow memory of the next step.
+// Pulled offsets of a node on the domain edge, through the boundary rules; outlet_in
+// is the outflow memory of the previous step.  The source of every direction is
+// resolved first (pure arithmetic: the rules of pull_rules, with the convective outflow
+// reading its value one node in), then the nine loads are issued together, so an edge
+// node costs one memory round trip like an interior one.  When update_outlet is set,
+// the east column stores its pulled values 3, 6, 7 into d.outlet_out as the memory of
+// the next step (in place when outlet_out == outlet_in: each element is read and
+// written by the same thread).
+// A uniform value held in a scalar register.  Selecting between two such values keeps
+// the choice in registers; selecting between two loads would let the compiler turn it
+// into one load from a per-lane address, a memory round trip on the critical path.
+__device__ __forceinline__ float uniform_value(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uniform_value(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <class S>
-__device__ void pull_edge(const SimDesc& d, const void* fin, int i, int j,
+__device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_in, int i, int j,
                           typename Codec<S>::T g[NQ], bool update_outlet) {
     using T = typename Codec<S>::T;
     const Consts<T>& c = consts_of<T>(d);
-    T* outlet = reinterpret_cast<T*>(d.outlet);
+    const int nx = d.nx, ny = d.ny;
+    // boundary kinds as uniform values: no lane-dependent indexing into memory
+    const int kW = d.bc[0], kE = d.bc[1], kS = d.bc[2], kN = d.bc[3];
+    const char* src[NQ];
+    unsigned off[NQ];
+    T add[NQ];
+    bool outflow[NQ];
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
-        T v;
-        if (!pull_rules<S>(d, fin, a, i, j, v)) {
-            // convective outflow: implicit upwind step of df/dt + U_c df/dx = 0 using
-            // last step's value at the east column and this step's value one node in
-            T qv;
-            pull_rules<S>(d, fin, a, d.nx - 2, j, qv);
-            v = (outlet[outflow_slot(a) * d.ny + j] + c.uc * qv) * c.inv1uc;
+        int si = i - dir_cx(a), sj = j - dir_cy(a);
+        int pi = i;  // node whose pull this is (nx - 2 for the outflow's inner value)
+        bool fx = false, fy = false, bb = false, of = false;
+        T bbv = T(0);
+        if (si < 0 || si >= nx) {
+            const bool west = si < 0;
+            const int kind = west ? kW : kE;
+            if (kind == BC_PERIODIC) {
+                si += west ? nx : -nx;
+            } else if (kind == BC_SYMMETRY) {
+                fx = true;
+                si = i;
+            } else if (kind == BC_OUTFLOW) {
+                of = true;  // value pulled by (nx - 2, j): its x source is in range
+                pi = nx - 2;
+                si = nx - 2 - dir_cx(a);
+            } else {  // WALL or VELOCITY: half-way bounce-back at (i, j)
+                bb = true;
+                bbv = west ? uniform_value(c.bb[0][a]) : uniform_value(c.bb[1][a]);
+            }
         }
-        g[a] = v;
+        if (!bb && (sj < 0 || sj >= ny)) {
+            const bool south = sj < 0;
+            const int kind = south ? kS : kN;
+            if (kind == BC_PERIODIC) {
+                sj += south ? ny : -ny;
+            } else if (kind == BC_SYMMETRY) {
+                fy = true;
+                sj = j;
+            } else {
+                bb = true;
+                bbv = south ? uniform_value(c.bb[2][a]) : uniform_value(c.bb[3][a]);
+            }
+        }
+        const int ax = dir_flip_x(a), ay = dir_flip_y(a), ao = dir_opp(a);
+        int dir;
+        T ad;
+        if (bb) {
+            dir = ao;
+            si = pi;
+            sj = j;
+            ad = bbv;
+        } else if (fx && fy) {  // specular reflection between directions
+            dir = ao;
+            ad = uniform_value(c.dref[a][ao]);
+        } else if (fx) {
+            dir = ax;
+            ad = ax != a ? uniform_value(c.dref[a][ax]) : T(0);
+        } else if (fy) {
+            dir = ay;
+            ad = ay != a ? uniform_value(c.dref[a][ay]) : T(0);
+        } else {
+            dir = a;
+            ad = T(0);
+        }
+        src[a] = plane<S>(d, fin, dir);
+        off[a] = node_off<S>(d, si, sj);
+        add[a] = ad;
+        outflow[a] = of;
     }
-    if (update_outlet && i == d.nx - 1 && d.bc[1] == BC_OUTFLOW) {
-        outlet[0 * d.ny + j] = g[3];
-        outlet[1 * d.ny + j] = g[6];
-        outlet[2 * d.ny + j] = g[7];
+    T v[NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) v[a] = Codec<S>::load(src[a], off[a], d.inv_scale);
+    const T* outlet = reinterpret_cast<const T*>(outlet_in);
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+        T x = v[a] + add[a];
+        // convective outflow: implicit upwind step of df/dt + U_c df/dx = 0 using last
+        // step's value at the east column and this step's value one node in
+        if (outflow[a]) x = (outlet[outflow_slot(a) * ny + j] + c.uc * x) * c.inv1uc;
+        g[a] = x;
+    }
+    if (update_outlet && i == nx - 1 && kE == BC_OUTFLOW) {
+        T* next = reinterpret_cast<T*>(d.outlet_out);
+        next[0 * ny + j] = g[3];
+        next[1 * ny + j] = g[6];
+        next[2 * ny + j] = g[7];
     }
 }
 
@@ -491,78 +601,45 @@ __device__ __forceinline__ void rk4_dof(double Mq, double cq, double kq, double 
     v = u + (k1v + 2.0 * k2v + 2.0 * k3v + k4v) / 6.0;
 }
 
-// Finalise one step: record it and advance the body (reads [p], writes [p ^ 1]).
-// tot = (F_vp x, y, T_vp, P_in x, y, theta after collision, the same before it).
-// The hydrodynamic load is F_vp + P_in(n) - P_in(n-1): with P_in the post-collision
-// momentum inside the body this is, for a sharp indicator, the momentum carried
-// across the interface by streaming (the momentum-exchange force of Eqs. (25)-(27));
-// on the first step after the body is set the pre-collision momentum stands in for
-// P_in(n-1).
-// Advance a body state by one step given that step's FP64 sums
-// tot = (F_vp x, y, T_vp, P_in x, y, theta after collision, the same before it), and
-// produce the step's record.  The hydrodynamic load is F_vp + P_in(n) - P_in(n-1): with
-// P_in the post-collision momentum inside the body this is, for a sharp indicator, the
-// momentum carried across the interface by streaming (the momentum-exchange force of
-// Eqs. (25)-(27)); on the first step after the body is set the pre-collision momentum
-// stands in for P_in(n-1).
-__device__ __noinline__ void state_advance(const BodyDev& B, const BodyState& prev, const double tot[NRED],
-                                     BodyState& next, Record& r) {
-    r.step = prev.step;
-    r.fvp[0] = tot[0];
-    r.fvp[1] = tot[1];
-    r.tvp = tot[2];
-    r.pin[0] = tot[3];
-    r.pin[1] = tot[4];
-    r.pin[2] = tot[5];
-    double dp[3] = {0.0, 0.0, 0.0};
-    if (B.imc)
-        for (int k = 0; k < 3; ++k)
-            dp[k] = tot[3 + k] - (prev.pin_valid ? prev.pin_prev[k] : tot[6 + k]);
-    r.fh[0] = tot[0] + dp[0];
-    r.fh[1] = tot[1] + dp[1];
-    r.th = tot[2] + dp[2];
-    double q[3], v[3];
-    for (int k = 0; k < 3; ++k) {
-        q[k] = prev.q[k];
-        v[k] = prev.v[k];
-        r.q[k] = q[k];
-        r.v[k] = v[k];
-    }
-    next.t_body = prev.t_body + 1;
-    if (B.active) {
-        if (B.mode == MODE_IMPOSED_SIN) {
-            const double w = 6.283185307179586476925286766559 * B.freq;
-            const double ph = w * (double)next.t_body;
-            q[1] = B.y0 + B.amp * sin(ph);
-            v[1] = w * B.amp * cos(ph);
-        } else if (B.mode == MODE_CONST_VEL) {
-            for (int k = 0; k < 3; ++k) q[k] += v[k];
-        } else if (B.mode == MODE_FREE) {
-            const double F[3] = {r.fh[0], r.fh[1], r.th};
-            for (int k = 0; k < 3; ++k) {
-                if (!(B.free_mask & (1u << k))) continue;
-                rk4_dof(k < 2 ? B.mass : B.inertia, B.c[k], B.k[k], B.q0[k], F[k] + B.fext[k],
-                        q[k], v[k]);
-            }
-        }
-    }
-    for (int k = 0; k < 3; ++k) {
-        next.q[k] = q[k];
-        next.v[k] = v[k];
-        next.pin_prev[k] = tot[3 + k];
-    }
-    next.pin_valid = 1;
-    next.step = prev.step + 1;
-}
+// Working set, in LDS, of the body update that ends a step.
+struct BodyStep {
+    double tot[NRED];  // the step's FP64 sums
+    double F[3];       // load used by the body update (F_h x, y and T_h)
+    double q[3], v[3]; // state of the next step
+    long long step, t_body;
+    int boxM[4];
+};
 
 __device__ __forceinline__ bool box_inside(const int a[4], const int b[4]) {
     return a[0] >= b[0] && a[1] <= b[1] && a[2] >= b[2] && a[3] <= b[3];
 }
 
+// Lanes of a 64-lane wave moved by one DPP pattern (lanes reading outside their row, or
+// masked off, receive 0); the 64-bit value moves as two 32-bit halves.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, BANK_MASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, BANK_MASK, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Row shifts build the sum of
+// each 16-lane row in its last lane, row broadcasts carry it on to lane 63 (a fixed
+// order of FP64 additions, the same in every wave), which is then read by all lanes.
+// Data-parallel moves between lanes: no LDS round trips.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    double t = v + dpp_move<0x111, 0xf, 0xf>(v);   // row_shr:1
+    t = t + dpp_move<0x112, 0xf, 0xf>(v);          // row_shr:2
+    t = t + dpp_move<0x113, 0xf, 0xf>(v);          // row_shr:3
+    t = t + dpp_move<0x114, 0xf, 0xe>(t);          // row_shr:4, banks 1-3
+    t = t + dpp_move<0x118, 0xf, 0xc>(t);          // row_shr:8, banks 2-3
+    t = t + dpp_move<0x142, 0xa, 0xf>(t);          // row_bcast:15, rows 1 and 3
+    t = t + dpp_move<0x143, 0xc, 0xf>(t);          // row_bcast:31, rows 2 and 3
+    const long long b = __builtin_bit_cast(long long, t);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
 // ---- one tile of one step ------------------------------------------------------------
@@ -570,9 +647,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 // next row's nine loads before colliding the current row.  Nodes are pulled,
 // penalized, collided and stored.  PART tiles (those meeting the body) also rasterise
 // chi and u_s and accumulate force, torque and internal momentum in FP64.
+// First row of a tile: the pulled offsets of node (i, j0), interior or edge.
+template <class S>
+__device__ __forceinline__ void pull_first(const SimDesc& d, int p, int tx, int ty, int rows,
+                                           typename Codec<S>::T g[NQ]) {
+    const int i = tx * TILE_X + (int)threadIdx.x;
+    const int j0 = ty * rows;
+    // a wave with any edge node takes the boundary-rule pull for all its lanes (it
+    // handles interior nodes too): one path and one round of loads per wave
+    const bool inner = i >= 1 && i <= d.nx - 2 && j0 >= 1 && j0 <= d.ny - 2;
+    if (__all(inner)) {
+        const char* P[NQ];
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) P[a] = plane<S>(d, d.pop[p], a);
+        pull_interior<S>(P, node_off<S>(d, i, j0), (unsigned)d.pitch * (unsigned)sizeof(S),
+                         d.inv_scale, g);
+    } else if (i < d.nx && j0 < d.ny) {
+        pull_edge<S>(d, d.pop[p], d.outlet, i, j0, g, true);
+    }
+}
+
 template <class S, int ROWS, bool NT, bool PART>
 __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int p,
-                                          double acc[NRED], const double* pose) {
+                                          double acc[NRED], const double* pose,
+                                          typename Codec<S>::T g[NQ]) {
     using T = typename Codec<S>::T;
     const Consts<T>& c = consts_of<T>(d);
     const void* fin = d.pop[p];
@@ -584,27 +682,25 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
     const bool col_inner = i >= 1 && i <= nx - 2;
 
     const char* P[NQ];
+    char* Q[NQ];
 #pragma unroll
-    for (int a = 0; a < NQ; ++a) P[a] = plane<S>(d, fin, a);
+    for (int a = 0; a < NQ; ++a) {
+        P[a] = plane<S>(d, fin, a);
+        Q[a] = fout + (long long)a * d.ps * (long long)sizeof(S);
+    }
     const unsigned rowb = (unsigned)d.pitch * (unsigned)sizeof(S);
     const float is = d.inv_scale;
 
-    T g[NQ], gn[NQ];
-    if (col_ok && j0 < ny) {
-        if (col_inner && j0 >= 1 && j0 <= ny - 2)
-            pull_interior<S>(P, node_off<S>(d, i, j0), rowb, is, g);
-        else
-            pull_edge<S>(d, fin, i, j0, g, true);
-    }
+    T gn[NQ];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int j = j0 + r;
         if (j >= ny) break;  // uniform over the workgroup
-        if (r + 1 < ROWS && j + 1 < ny && col_ok) {
-            if (col_inner && j + 1 <= ny - 2)
+        if (r + 1 < ROWS && j + 1 < ny) {  // uniform
+            if (__all(col_inner && j + 1 <= ny - 2))
                 pull_interior<S>(P, node_off<S>(d, i, j + 1), rowb, is, gn);
-            else
-                pull_edge<S>(d, fin, i, j + 1, gn, true);
+            else if (col_ok)
+                pull_edge<S>(d, fin, d.outlet, i, j + 1, gn, true);
         }
         if (col_ok) {
             T out[NQ];
@@ -645,9 +741,7 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
             }
             const unsigned off = node_off<S>(d, i, j);
 #pragma unroll
-            for (int a = 0; a < NQ; ++a)
-                Codec<S>::template store<NT>(fout + (long long)a * d.ps * (long long)sizeof(S), off,
-                                             out[a], d.scale);
+            for (int a = 0; a < NQ; ++a) Codec<S>::template store<NT>(Q[a], off, out[a], d.scale);
             if (!(o.rho > T(0)) || !__builtin_isfinite(o.ux) || !__builtin_isfinite(o.uy))
                 atomicOr(d.flag, 1);
         }
@@ -658,10 +752,10 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
     }
 }
 
-// Fixed-order FP64 sum of a step's partial slots by one workgroup of TILE_X threads;
-// every caller obtains bitwise the same totals.  Result in tot (all threads).
+// Fixed-order FP64 sum of a step's partial slots by one workgroup of TILE_X threads
+// into tot (LDS); every caller obtains bitwise the same totals.
 __device__ __forceinline__ void sum_slots(const double* __restrict__ slots, int nb,
-                                          double red[NWAVE][NRED], double tot[NRED]) {
+                                          double red[NWAVE][NRED], double* tot) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double t[NRED];
 #pragma unroll
@@ -670,35 +764,108 @@ __device__ __forceinline__ void sum_slots(const double* __restrict__ slots, int 
         for (int k = 0; k < NRED; ++k) t[k] += slots[(long long)s * NRED + k];
 #pragma unroll
     for (int k = 0; k < NRED; ++k) {
-        const double s = wave_sum(t[k]);
-        if (lane == 0) red[wave][k] = s;
+        const double v = wave_sum(t[k]);
+        if (lane == 0) red[wave][k] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NRED; ++k) {
-        double s = red[0][k];
-        for (int w = 1; w < NWAVE; ++w) s += red[w][k];
-        tot[k] = s;
+    if (threadIdx.x < NRED) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int w = 1; w < NWAVE; ++w) v += red[w][k];
+        tot[k] = v;
     }
     __syncthreads();
 }
 
 __device__ __forceinline__ int box_count(const int b[4]) { return (b[1] - b[0] + 1) * (b[3] - b[2] + 1); }
 
-// State of step n (parity p) from the state and partial sums of step n - 1, as every
-// participating tile and the flush kernel compute it.  Thread 0 returns next/rec.
-__device__ __forceinline__ void derive_state(const SimDesc& d, int p, double red[NWAVE][NRED],
-                                             BodyState& next, Record& rec) {
+// The body update at the end of step n - 1 (Sec. 2.3, Eqs. (23)-(24); RK4 of
+// Algorithm 1), as every participating tile of step n and the flush kernel compute it:
+// the fixed-order sum of step n - 1's slots, then one lane per degree of freedom
+// advances it.  The hydrodynamic load is F_vp + P_in(n-1) - P_in(n-2): with P_in the
+// post-collision momentum inside the body this is, for a sharp indicator, the momentum
+// carried across the interface by streaming (the momentum-exchange force of Eqs.
+// (25)-(27)); on the first step after the body is set the pre-collision momentum stands
+// in for the previous P_in.  The result is left in bs (LDS) for all threads; the work
+// runs in parallel lanes so that it needs no stack and few registers.
+__device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[NWAVE][NRED],
+                                            BodyStep& bs) {
     const BodyDev& B = *d.body;
     const BodyState& prev = B.st[p ^ 1];
-    double tot[NRED];
-    sum_slots(d.partials + (long long)(p ^ 1) * d.part_stride, box_count(prev.part_box), red, tot);
-    if (threadIdx.x == 0) {
-        state_advance(B, prev, tot, next, rec);
-        body_tiles(d.nx, d.ny, d.rows, B, next.q[0], next.q[1], next.boxM);
-        next.fresh = 0;
-        for (int k = 0; k < 4; ++k) next.part_box[k] = prev.boxM[k];
+    // the lanes that advance a degree of freedom read its previous state first, so that
+    // these loads and the slot loads below return together
+    const int k = threadIdx.x;
+    const int kk = k < 3 ? k : 0;
+    const double q_prev = prev.q[kk], v_prev = prev.v[kk], pin_prev = prev.pin_prev[kk];
+    const int pin_valid = prev.pin_valid;
+    const long long t_prev = prev.t_body, step_prev = prev.step;
+    sum_slots(d.partials + (long long)(p ^ 1) * d.part_stride, box_count(prev.part_box), red,
+              bs.tot);
+    if (k < 3) {
+        double dp = 0.0;
+        if (B.imc) dp = bs.tot[3 + k] - (pin_valid ? pin_prev : bs.tot[6 + k]);
+        const double F = bs.tot[k] + dp;
+        bs.F[k] = F;
+        double q = q_prev, v = v_prev;
+        if (B.active) {
+            if (B.mode == MODE_IMPOSED_SIN) {
+                if (k == 1) {
+                    const double w = 6.283185307179586476925286766559 * B.freq;
+                    const double ph = w * (double)(t_prev + 1);
+                    q = B.y0 + B.amp * sin(ph);
+                    v = w * B.amp * cos(ph);
+                }
+            } else if (B.mode == MODE_CONST_VEL) {
+                q += v;
+            } else if (B.mode == MODE_FREE && (B.free_mask & (1u << k))) {
+                rk4_dof(k < 2 ? B.mass : B.inertia, B.c[k], B.k[k], B.q0[k], F + B.fext[k], q, v);
+            }
+        }
+        bs.q[k] = q;
+        bs.v[k] = v;
+    } else if (k == 3) {
+        bs.step = step_prev + 1;
+        bs.t_body = t_prev + 1;
     }
+    __syncthreads();
+    if (k == 0) body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], bs.boxM);
+    __syncthreads();
+}
+
+// Record of step n - 1 (one thread), from the state it used and its sums.
+__device__ __forceinline__ void write_record(const SimDesc& d, const BodyState& prev,
+                                             const BodyStep& bs) {
+    Record& r = d.hist[prev.step % d.hist_cap];
+    r.step = prev.step;
+    r.fvp[0] = bs.tot[0];
+    r.fvp[1] = bs.tot[1];
+    r.tvp = bs.tot[2];
+    for (int k = 0; k < 3; ++k) {
+        r.pin[k] = bs.tot[3 + k];
+        r.q[k] = prev.q[k];
+        r.v[k] = prev.v[k];
+    }
+    r.fh[0] = bs.F[0];
+    r.fh[1] = bs.F[1];
+    r.th = bs.F[2];
+}
+
+// State slot of step n from the derived update (one thread); fresh marks a flush.
+__device__ __forceinline__ void store_state(BodyState& cur, const BodyState& prev,
+                                            const BodyStep& bs, int fresh) {
+    for (int k = 0; k < 3; ++k) {
+        cur.q[k] = bs.q[k];
+        cur.v[k] = bs.v[k];
+        cur.pin_prev[k] = bs.tot[3 + k];
+    }
+    cur.t_body = bs.t_body;
+    cur.step = bs.step;
+    cur.pin_valid = 1;
+    for (int k = 0; k < 4; ++k) {
+        cur.boxM[k] = bs.boxM[k];
+        cur.part_box[k] = fresh ? bs.boxM[k] : prev.boxM[k];
+    }
+    cur.fresh = fresh;
 }
 
 // Tiles that meet the body (with a margin, judged from the previous pose) obtain this
@@ -706,25 +873,35 @@ __device__ __forceinline__ void derive_state(const SimDesc& d, int p, double red
 // the next step (or a flush) adds the slots in a fixed order.  No device-wide fence is
 // needed: the kernel boundary orders producer and consumer (on this multi-XCD part such
 // a fence would write back the whole L2).
-// Workgroup (bx, by) of a tiles_x x tiles_y launch handles tile column tx = bx and
-// tile row ty = (by + by0) mod tiles_y: the rows of the participation box are
-// dispatched first, so the longer body work of their tiles overlaps the rest of the
-// grid instead of extending the end of the kernel.
+// The caller maps workgroups to tiles (the host rotates the rows so that those of the
+// body come first in dispatch order: their longer work then overlaps the rest of the
+// grid instead of extending the end of the kernel).
 template <class S, int ROWS, bool NT>
-__device__ __forceinline__ void step_tile(const SimDesc& d, int bx, int by, int p) {
+__device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p) {
+    using T = typename Codec<S>::T;
     __shared__ double red[NWAVE][NRED];
     __shared__ double pose[6];
+    __shared__ BodyStep bs;
     BodyDev& B = *d.body;
+    // the participation box (both parities read, then selected: no dependent load), then
+    // the first row's populations, which stay in flight while the box is tested
     const int fresh = B.st[p].fresh;
-    const int* pb = fresh ? B.st[p].boxM : B.st[p ^ 1].boxM;
+    int box_p[4], box_q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        box_p[k] = B.st[p].boxM[k];
+        box_q[k] = B.st[p ^ 1].boxM[k];
+    }
+    T g[NQ];
+    pull_first<S>(d, p, tx, ty, ROWS, g);
+    int pb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pb[k] = fresh ? box_p[k] : box_q[k];
     const int bx0 = pb[0], bx1 = pb[1], by0 = pb[2], by1 = pb[3];
-    const int tx = bx;
-    int ty = by + by0;
-    if (ty >= d.tiles_y) ty -= d.tiles_y;
     const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
     double acc[NRED];
     if (!part) {
-        step_rows<S, ROWS, NT, false>(d, tx, ty, p, acc, nullptr);
+        step_rows<S, ROWS, NT, false>(d, tx, ty, p, acc, nullptr, g);
         return;  // uniform over the workgroup
     }
     const bool writer = tx == bx0 && ty == by0;
@@ -734,40 +911,16 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int bx, int by, int 
             pose[3 + threadIdx.x] = B.st[p].v[threadIdx.x];
         }
     } else {
-        BodyState next;
-        Record rec;
-        derive_state(d, p, red, next, rec);
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < 3; ++k) {
-                pose[k] = next.q[k];
-                pose[3 + k] = next.v[k];
-            }
-            if (writer) {
-                int exact[4];
-                body_tiles(d.nx, d.ny, d.rows, B, next.q[0], next.q[1], exact, 1.0);
-                if (!box_inside(exact, pb)) atomicOr(d.flag, 2);  // moved >= 2 nodes in a step
-                d.hist[rec.step % d.hist_cap] = rec;
-                BodyState& cur = B.st[p];
-                for (int k = 0; k < 3; ++k) {
-                    cur.q[k] = next.q[k];
-                    cur.v[k] = next.v[k];
-                    cur.pin_prev[k] = next.pin_prev[k];
-                }
-                cur.t_body = next.t_body;
-                cur.step = next.step;
-                cur.pin_valid = next.pin_valid;
-                for (int k = 0; k < 4; ++k) {
-                    cur.boxM[k] = next.boxM[k];
-                    cur.part_box[k] = next.part_box[k];
-                }
-            }
+        derive_body(d, p, red, bs);
+        if (threadIdx.x < 3) {
+            pose[threadIdx.x] = bs.q[threadIdx.x];
+            pose[3 + threadIdx.x] = bs.v[threadIdx.x];
         }
     }
-    if (writer && threadIdx.x == 0) B.st[p ^ 1].fresh = 0;  // the next step derives its state
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
-    step_rows<S, ROWS, NT, true>(d, tx, ty, p, acc, pose);
+    step_rows<S, ROWS, NT, true>(d, tx, ty, p, acc, pose, g);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -783,6 +936,18 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int bx, int by, int 
         const int slot = (ty - by0) * (bx1 - bx0 + 1) + (tx - bx0);
         d.partials[(long long)p * d.part_stride + (long long)slot * NRED + k] = s;
     }
+    // the writer's global stores come last: no barrier waits for them
+    if (writer && threadIdx.x == 0) {
+        if (!fresh) {
+            const BodyState& prev = B.st[p ^ 1];
+            int exact[4];
+            body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], exact, 1.0);
+            if (!box_inside(exact, pb)) atomicOr(d.flag, 2);  // moved >= 2 nodes in a step
+            write_record(d, prev, bs);
+            store_state(B.st[p], prev, bs, 0);
+        }
+        B.st[p ^ 1].fresh = 0;  // the next step derives its state
+    }
 }
 
 // Flush (one workgroup): make the state of step n (parity p) final on the host's
@@ -790,19 +955,17 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int bx, int by, int 
 // already, so it may be launched any number of times.
 __device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
     __shared__ double red[NWAVE][NRED];
+    __shared__ BodyStep bs;
     BodyDev& B = *d.body;
     if (B.st[p].fresh) return;  // uniform
-    BodyState next;
-    Record rec;
-    derive_state(d, p, red, next, rec);
+    derive_body(d, p, red, bs);
     if (threadIdx.x == 0) {
+        const BodyState& prev = B.st[p ^ 1];
         int exact[4];
-        body_tiles(d.nx, d.ny, d.rows, B, next.q[0], next.q[1], exact, 1.0);
-        if (!box_inside(exact, next.part_box)) atomicOr(d.flag, 2);
-        d.hist[rec.step % d.hist_cap] = rec;
-        next.fresh = 1;
-        for (int k = 0; k < 4; ++k) next.part_box[k] = next.boxM[k];
-        B.st[p] = next;
+        body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], exact, 1.0);
+        if (!box_inside(exact, prev.boxM)) atomicOr(d.flag, 2);
+        write_record(d, prev, bs);
+        store_state(B.st[p], prev, bs, 1);
     }
 }
 

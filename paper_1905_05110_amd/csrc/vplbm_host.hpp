@@ -1,0 +1,99 @@
+// vplbm_host.hpp -- host-side state of a simulation, shared by the translation units
+// of the host runtime (vplbm.hip: step, batch and I/O; adjoint_host.hip: the adjoint).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "vplbm.h"
+#include "vplbm_kernels.hpp"
+
+namespace vplbm {
+
+inline size_t elem_size(int storage) {
+    switch (storage) {
+        case LBM_FP64: return 8;
+        case LBM_FP32: return 4;
+        default: return 2;
+    }
+}
+
+inline int row_pitch(int nx) { return (nx + 63) / 64 * 64; }
+
+inline long long plane_stride(int nx, int ny) {
+    // pad planes by 5 x 64 elements so the nine streams do not start on the same
+    // large power-of-two boundary
+    return (long long)row_pitch(nx) * ny + 320;
+}
+
+}  // namespace vplbm
+
+using vplbm::BodyDev;
+using vplbm::Record;
+using vplbm::SimDesc;
+using vplbm::bf16s;
+
+struct lbm_sim {
+    int nx = 0, ny = 0, storage = LBM_FP32;
+    size_t pop_bytes = 0;
+    void* pop[2] = {nullptr, nullptr};
+    bool own_pop = false;
+    void* outlet = nullptr;
+    BodyDev* body_d = nullptr;
+    double* partials = nullptr;
+    Record* hist = nullptr;
+    int* flag = nullptr;
+    double* staging = nullptr;  // FP64 [9][ny][nx] for set/get/fields
+    SimDesc desc{};
+    SimDesc* desc_d = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t host_step = 0;
+    int64_t drained = 0;
+    int64_t rec_end = 0;  // without a body: records exist for the steps before this one
+    int hist_cap = 65536;
+    lbm_opts opts{};
+    lbm_rates rates{};
+    double eta = 0.0;
+    BodyDev body_h{};
+    lbm_body body_desc{};  // last body set (used by the autotuner)
+    bool has_body = false;
+    std::string err;
+    int graph_steps = 0;
+    int rows = 1;   // rows of a tile (nodes per lane)
+    bool nt = false;  // nontemporal population stores
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool in_batch = false;  // member of an lbm_batch: stepped, configured and freed by it
+    int row_shift = 0;      // first tile row dispatched: that of the body when it was set
+};
+
+#define HIP_TRY(sim, expr)                                                             \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (sim)->err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+            return LBM_ERR_HIP;                                                        \
+        }                                                                              \
+    } while (0)
+
+inline int fail(lbm_sim* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+inline int reject_member(lbm_sim* s) {
+    return fail(s, LBM_ERR_STATE, "a member of a batch is stepped, configured and freed by its batch");
+}
+
+
+template <class F>
+inline int dispatch(int storage, F&& f) {
+    switch (storage) {
+        case LBM_FP64: return f((double*)nullptr);
+        case LBM_FP32: return f((float*)nullptr);
+        case LBM_FP16_OFS: return f((_Float16*)nullptr);
+        default: return f((bf16s*)nullptr);
+    }
+}

@@ -14,8 +14,9 @@ namespace vplbm {
 template <class S>
 struct Launch {
     // the kernel of one time step (parity p; rows per tile 1, 2 or 4; nt selects
-    // nontemporal stores)
-    static void step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p, hipStream_t st);
+    // nontemporal stores; tile rows dispatched from row_shift on, 0 <= row_shift < grid.y)
+    static void step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p, hipStream_t st,
+                     int row_shift = 0);
     // one time step of several simulations in one launch: workgroup b handles the tile
     // sched[b] = (simulation, by << 16 | bx) of descs[simulation]
     static void step_batch(const SimDesc* descs, const int2* sched, int nsched, int rows, bool nt,
@@ -27,26 +28,34 @@ struct Launch {
 };
 
 // ---------------------------------------------------------------------------------
-// (A floor of 8 waves per SIMD forces spills into the body path and measured slower.)
-template <class S, int ROWS, bool NT>
-// One kernel serves a single simulation (sched == nullptr, 2D grid of its tiles) and a
-// batch (1D grid over sched).  The tile body has a single call site, so a simulation
+// One kernel serves a single simulation (sched == nullptr, 2D grid of its tiles, tile
+// row (blockIdx.y + row_shift) mod tiles_y) and a batch (1D grid over sched, whose
+// order the host chooses).  The tile body has a single call site, so a simulation
 // computes bitwise the same inside a batch as alone.
-__global__ __launch_bounds__(TILE_X) void k_step(const SimDesc* __restrict__ descs,
-                                                 const int2* __restrict__ sched, int p) {
+// Single-row tiles of 4-byte or narrower storage fit in 64 registers without spilling:
+// eight waves per SIMD then hide more memory latency.
+template <class S, int ROWS>
+constexpr int step_waves() { return (sizeof(S) <= 4 && ROWS == 1) ? 8 : 1; }
+
+template <class S, int ROWS, bool NT>
+__global__ __launch_bounds__(TILE_X) __attribute__((amdgpu_waves_per_eu(step_waves<S, ROWS>())))
+void k_step(const SimDesc* __restrict__ descs,
+                                                 const int2* __restrict__ sched, int p,
+                                                 int row_shift) {
     const SimDesc* d;
-    int bx, by;
-    if (sched) {  // entry: (simulation, by << 16 | bx)
+    int tx, ty;
+    if (sched) {  // entry: (simulation, ty << 16 | tx)
         const int2 e = sched[blockIdx.x];
         d = descs + e.x;
-        bx = e.y & 0xffff;
-        by = e.y >> 16;
+        tx = e.y & 0xffff;
+        ty = e.y >> 16;
     } else {
         d = descs;
-        bx = (int)blockIdx.x;
-        by = (int)blockIdx.y;
+        tx = (int)blockIdx.x;
+        ty = (int)blockIdx.y + row_shift;
+        if (ty >= (int)gridDim.y) ty -= (int)gridDim.y;
     }
-    step_tile<S, ROWS, NT>(*d, bx, by, p);
+    step_tile<S, ROWS, NT>(*d, tx, ty, p);
 }
 
 __global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p);
@@ -105,7 +114,7 @@ __global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     T g[NQ];
-    pull_edge<S>(d, d.pop[p], i, j, g, false);
+    pull_edge<S>(d, d.pop[p], d.outlet, i, j, g, false);
     const BodyDev& B = *d.body;
     const BodyState& st = B.st[p];  // final: the host flushes before reading fields
     double chi = 0.0, dsx = 0.0, dsy = 0.0;
@@ -130,11 +139,11 @@ inline dim3 grid_rows(const SimDesc& d) { return dim3((d.nx + 255) / 256, d.ny);
 
 template <class S, bool NT>
 static void launch_step_rows(const SimDesc* dd, const int2* sched, dim3 grid, int rows, int p,
-                             hipStream_t st) {
+                             hipStream_t st, int row_shift) {
     switch (rows) {
-        case 1: hipLaunchKernelGGL((k_step<S, 1, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p); break;
-        case 2: hipLaunchKernelGGL((k_step<S, 2, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p); break;
-        default: hipLaunchKernelGGL((k_step<S, 4, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p); break;
+        case 1: hipLaunchKernelGGL((k_step<S, 1, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p, row_shift); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p, row_shift); break;
+        default: hipLaunchKernelGGL((k_step<S, 4, NT>), grid, dim3(TILE_X), 0, st, dd, sched, p, row_shift); break;
     }
 }
 
@@ -142,19 +151,19 @@ static void launch_step_rows(const SimDesc* dd, const int2* sched, dim3 grid, in
 #define VPLBM_DEFINE_LAUNCH(S)                                                                \
     template <>                                                                             \
     void Launch<S>::step(const SimDesc* dd, dim3 grid, int rows, bool nt, int p,            \
-                         hipStream_t st) {                                                  \
+                         hipStream_t st, int row_shift) {                                   \
         if (nt)                                                                             \
-            launch_step_rows<S, true>(dd, nullptr, grid, rows, p, st);                      \
+            launch_step_rows<S, true>(dd, nullptr, grid, rows, p, st, row_shift);           \
         else                                                                                \
-            launch_step_rows<S, false>(dd, nullptr, grid, rows, p, st);                     \
+            launch_step_rows<S, false>(dd, nullptr, grid, rows, p, st, row_shift);          \
     }                                                                                       \
     template <>                                                                             \
     void Launch<S>::step_batch(const SimDesc* descs, const int2* sched, int nsched, int rows, \
                                bool nt, int p, hipStream_t st) {                            \
         if (nt)                                                                             \
-            launch_step_rows<S, true>(descs, sched, dim3(nsched), rows, p, st);             \
+            launch_step_rows<S, true>(descs, sched, dim3(nsched), rows, p, st, 0);          \
         else                                                                                \
-            launch_step_rows<S, false>(descs, sched, dim3(nsched), rows, p, st);            \
+            launch_step_rows<S, false>(descs, sched, dim3(nsched), rows, p, st, 0);         \
     }                                                                                       \
     template <>                                                                             \
     void Launch<S>::fill(const SimDesc& d, const double g[NQ], int buf, hipStream_t st) {   \

@@ -30,7 +30,11 @@ EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "l
            "lbm_default_batch_opts", "lbm_batch_create", "lbm_batch_step",
            "lbm_batch_set_graph_steps", "lbm_batch_sync", "lbm_batch_sim", "lbm_batch_size",
            "lbm_batch_configure", "lbm_batch_autotune", "lbm_batch_destroy",
-           "lbm_batch_last_error"]
+           "lbm_batch_last_error",
+           "lbm_default_adjoint_opts", "lbm_adjoint_create", "lbm_adjoint_set_body",
+           "lbm_adjoint_set_initial", "lbm_adjoint_forward", "lbm_adjoint_forces",
+           "lbm_adjoint_backward", "lbm_adjoint_gradient", "lbm_adjoint_time_kernels",
+           "lbm_adjoint_destroy", "lbm_adjoint_last_error"]
 
 
 class LbmError(RuntimeError):
@@ -71,6 +75,11 @@ class BatchDesc(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("storage", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
                 ("order", C.c_int), ("hip_stream", C.c_void_p)]
+
+
+class AdjointOpts(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("checkpoint_every", C.c_int), ("weight_fx", C.c_double),
+                ("weight_fy", C.c_double)]
 
 
 RECORD_DTYPE = np.dtype([("step", "<i8"), ("fvp", "<f8", (2,)), ("tvp", "<f8"),
@@ -130,6 +139,20 @@ def load_library(path=LIB_PATH):
     L.lbm_batch_destroy.argtypes = [P]
     L.lbm_batch_last_error.argtypes = [P]
     L.lbm_batch_last_error.restype = C.c_char_p
+    L.lbm_default_adjoint_opts.argtypes = [C.POINTER(AdjointOpts)]
+    L.lbm_default_adjoint_opts.restype = None
+    L.lbm_adjoint_create.argtypes = [C.c_int, C.c_int, Rates, C.c_double, C.POINTER(Opts),
+                                     C.POINTER(Body), C.POINTER(AdjointOpts), C.POINTER(P)]
+    L.lbm_adjoint_set_body.argtypes = [P, C.POINTER(Body)]
+    L.lbm_adjoint_set_initial.argtypes = [P, _DP, _DP]
+    L.lbm_adjoint_forward.argtypes = [P, _DP]
+    L.lbm_adjoint_forces.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+    L.lbm_adjoint_backward.argtypes = [P]
+    L.lbm_adjoint_gradient.argtypes = [P, _DP, _DP, _DP]
+    L.lbm_adjoint_time_kernels.argtypes = [P, C.c_int, _DP, _DP]
+    L.lbm_adjoint_destroy.argtypes = [P]
+    L.lbm_adjoint_last_error.argtypes = [P]
+    L.lbm_adjoint_last_error.restype = C.c_char_p
     _LIB = L
     return L
 
@@ -427,3 +450,112 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Adjoint:
+    """Reverse-mode gradients of J = sum_{n<N} (w_x F_x(n) + w_y F_y(n)) for a body held
+    at a fixed pose: ``forward()`` runs N steps keeping checkpoints and returns J,
+    ``backward()`` sweeps them in reverse, ``gradient()`` returns dJ/dchi [ny, nx],
+    dJ/d(X, Y) and dJ/d(V_x, V_y, Omega)."""
+
+    def __init__(self, spec, body, steps, checkpoint_every=100, weights=(1.0, 0.0)):
+        L = load_library()
+        self.L, self.h = L, None
+        self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
+        self.spec = dict(spec)
+        self._opts = make_opts(spec)
+        self._body = make_body(body)
+        ao = AdjointOpts()
+        L.lbm_default_adjoint_opts(C.byref(ao))
+        ao.steps, ao.checkpoint_every = int(steps), int(checkpoint_every)
+        ao.weight_fx, ao.weight_fy = float(weights[0]), float(weights[1])
+        self.steps = int(steps)
+        h = C.c_void_p()
+        rc = L.lbm_adjoint_create(self.nx, self.ny, Rates(*[float(x) for x in spec["rates"]]),
+                                  float(spec["eta"]), C.byref(self._opts), C.byref(self._body),
+                                  C.byref(ao), C.byref(h))
+        if rc != LBM_OK:
+            raise LbmError(rc, L.lbm_adjoint_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.L.lbm_adjoint_last_error(self.h).decode())
+        return rc
+
+    def set_body(self, body):
+        self._body = make_body(body)
+        self._check(self.L.lbm_adjoint_set_body(self.h, C.byref(self._body)))
+
+    def set_initial(self, f=None, outlet=None):
+        fp = op = None
+        if f is not None:
+            f = np.ascontiguousarray(f, dtype=np.float64)
+            assert f.shape == (9, self.ny, self.nx)
+            fp = _ptr(f)
+        if outlet is not None:
+            outlet = np.ascontiguousarray(outlet, dtype=np.float64)
+            assert outlet.shape == (3, self.ny)
+            op = _ptr(outlet)
+        self._check(self.L.lbm_adjoint_set_initial(self.h, fp, op))
+
+    def forward(self):
+        J = C.c_double()
+        self._check(self.L.lbm_adjoint_forward(self.h, C.byref(J)))
+        return J.value
+
+    def forces(self):
+        out = np.zeros(self.steps, dtype=RECORD_DTYPE)
+        n = C.c_int64()
+        self._check(self.L.lbm_adjoint_forces(self.h, out.ctypes.data, self.steps, C.byref(n)))
+        return out[: n.value]
+
+    def backward(self):
+        self._check(self.L.lbm_adjoint_backward(self.h))
+
+    def gradient(self, chi=True):
+        g = np.zeros((self.ny, self.nx)) if chi else None
+        pos, vel = np.zeros(2), np.zeros(3)
+        self._check(self.L.lbm_adjoint_gradient(self.h, _ptr(g) if chi else None, _ptr(pos),
+                                                _ptr(vel)))
+        return dict(chi=g, pos=pos, vel=vel)
+
+    def time_kernels(self, reps=50):
+        a, s = C.c_double(), C.c_double()
+        self._check(self.L.lbm_adjoint_time_kernels(self.h, int(reps), C.byref(a), C.byref(s)))
+        return a.value, s.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_adjoint_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def body_position_objective():
+    """A ``torch.autograd.Function`` mapping the body centre (tensor of 2) to J, whose
+    backward runs the adjoint: ``J = Objective.apply(center, adjoint, body)``."""
+    import torch
+
+    class Objective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, center, adj, body):
+            c = center.detach().double().cpu().numpy()
+            adj.set_body(dict(body, x=float(c[0]), y=float(c[1])))
+            J = adj.forward()
+            ctx.adj = adj
+            ctx.center_like = center
+            return center.new_tensor(J)
+
+        @staticmethod
+        def backward(ctx, grad):
+            ctx.adj.backward()
+            g = ctx.adj.gradient(chi=False)["pos"]
+            return grad * ctx.center_like.new_tensor(g), None, None
+
+    return Objective

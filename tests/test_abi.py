@@ -136,3 +136,39 @@ def test_batch_create_without_device_reports_hip_error(lib):
     assert lib.lbm_batch_create(2, descs, None, C.byref(h)) == vplbm.LBM_ERR_HIP
     assert lib.lbm_batch_last_error(None).decode()
     assert not h.value
+
+
+def _adj_create(lib, storage="fp64", mode="fixed", steps=8, every=4):
+    spec = dict(nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3, storage=storage)
+    o = vplbm.make_opts(spec)
+    b = vplbm.make_body(dict(radius=2.0, x=4.0, y=4.0, mode=mode, mass=1.0, inertia=1.0))
+    ao = vplbm.AdjointOpts()
+    lib.lbm_default_adjoint_opts(C.byref(ao))
+    ao.steps, ao.checkpoint_every = steps, every
+    h = C.c_void_p()
+    rc = lib.lbm_adjoint_create(10, 8, vplbm.Rates(1.6, 1.5, 1.9, 1.2), 1e-3, C.byref(o),
+                                C.byref(b), C.byref(ao), C.byref(h))
+    return rc, h, lib.lbm_adjoint_last_error(None).decode()
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(steps=10, every=4), "multiple"),
+    (dict(steps=9, every=3), "even"),
+    (dict(steps=0, every=4), "steps"),
+    (dict(mode="free"), "FIXED"),
+    (dict(storage="fp16"), "FP64 or FP32"),
+])
+def test_invalid_adjoint_arguments_are_rejected(lib, kw, frag):
+    rc, h, msg = _adj_create(lib, **kw)
+    assert rc == vplbm.LBM_ERR_ARG
+    assert frag in msg
+    assert not h.value
+
+
+def test_adjoint_null_handles_and_layout(lib):
+    assert C.sizeof(vplbm.AdjointOpts) == 8 + 8 + 8 + 8
+    J = C.c_double()
+    assert lib.lbm_adjoint_forward(None, C.byref(J)) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_adjoint_backward(None) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_adjoint_gradient(None, None, None, None) == vplbm.LBM_ERR_ARG
+    assert lib.lbm_adjoint_destroy(None) == vplbm.LBM_ERR_ARG
