@@ -81,13 +81,13 @@ def cpu_baseline(wl, target_seconds):
                 n, wl["spec"]["nx"], wl["spec"]["ny"], dt)}
 
 
-def kernel_source_hash():
+def kernel_source_hash(storage):
+    """Hash of the sources the step kernel of this storage is compiled from."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1905_05110_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in ("vplbm_device.hpp", "vplbm_kernels.hpp", "kern_%s.hip" % storage):
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -97,7 +97,7 @@ def traffic_for(path, storage, nx, ny, rows, nt):
     if not path or not os.path.exists(path):
         return None
     want = "%s %d %d %s %d" % (storage, nx, ny, rows, int(bool(nt)))
-    src = kernel_source_hash()
+    src = kernel_source_hash(storage)
     for line in open(path):
         f = line.split()
         # traffic <storage> <nx> <ny> <rows> <nt> <source-hash> <bytes-per-launch>
@@ -270,7 +270,7 @@ def run_adjoint(args):
     steps, every = wl["steps"], wl["checkpoint_every"]
     w = (1.0 / (steps * 0.5 * wl["U0"] ** 2 * wl["D"]), 0.0)
     nodes = wl["spec"]["nx"] * wl["spec"]["ny"]
-    adj = vplbm.Adjoint(wl["spec"], wl["body"], steps, every, w)
+    adj = vplbm.Adjoint(wl["spec"], wl["body"], steps, every, w, graphs=args.graph_steps != 0)
     print("adjoint warm-up", file=sys.stderr, flush=True)
     J = adj.forward()
     adj.backward()
@@ -302,7 +302,8 @@ def run_adjoint(args):
         "data": "synthetic (channel flow from a uniform inflow state; no dataset)",
         "config": {"workload": "adjoint_drag_1024x512", "nx": wl["spec"]["nx"],
                    "ny": wl["spec"]["ny"], "storage": args.storage, "D": wl["D"], "Re": 100,
-                   "steps": steps, "checkpoint_every": every, "indicator": "tanh, delta = 1"},
+                   "steps": steps, "checkpoint_every": every, "indicator": "tanh, delta = 1",
+                   "graphs": args.graph_steps != 0},
         "forward_s": round(fwd, 5), "backward_s": round(bwd, 5),
         "forward_mlups": round(nodes * steps / fwd / 1e6, 1),
         "backward_mlups": round(nodes * steps / bwd / 1e6, 1),

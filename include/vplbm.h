@@ -113,7 +113,7 @@ typedef struct {
     int history_cap;       /* force records kept on the device between drains (default 65536) */
     int offset_ref;        /* LBM_REF_INITIAL (default) or LBM_REF_REST */
     int rows_per_tile;     /* grid rows per 256-column tile (nodes per lane): 1, 2, 4;
-                              0 = default.  Each setting is deterministic; results of
+                              0 = default (1).  Each setting is deterministic; results of
                               different settings agree to rounding (kernel variants may
                               contract multiply-adds differently; FP64 force sums follow
                               the tile order). */
@@ -250,7 +250,7 @@ typedef struct {
 
 typedef struct {
     int storage;        /* LBM_FP64 / LBM_FP32 / LBM_FP16_OFS / LBM_BF16_OFS */
-    int rows_per_tile;  /* 0 (default), 1, 2 or 4 */
+    int rows_per_tile;  /* 0 (default: 1), 1, 2 or 4 */
     int store_mode;     /* LBM_STORE_* */
     int order;          /* LBM_ORDER_* */
     void* hip_stream;   /* NULL: the library creates one */
@@ -310,9 +310,11 @@ typedef struct {
     int checkpoint_every;  /* K >= 2, even */
     double weight_fx;      /* w_x */
     double weight_fy;      /* w_y */
+    int use_graphs;        /* 1: segments run as captured HIP graphs; 0: eager launches */
 } lbm_adjoint_opts;
 
-void lbm_default_adjoint_opts(lbm_adjoint_opts* o);  /* N = 4000, K = 100, w = (1, 0) */
+/* N = 4000, K = 100, w = (1, 0), graphs on */
+void lbm_default_adjoint_opts(lbm_adjoint_opts* o);
 
 /* Creates the simulation (arguments as lbm_create and lbm_set_body; opts may be NULL)
  * and the adjoint buffers.  The initial state is the uniform equilibrium (rho0, u0). */

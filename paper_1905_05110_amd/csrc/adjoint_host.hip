@@ -62,6 +62,7 @@ struct lbm_adjoint {
     int storage = LBM_FP32, nx = 0, ny = 0;
     int64_t steps = 0;
     int K = 0, nseg = 0;
+    bool graphs = true;
     double wx = 0.0, wy = 0.0;
     lbm_body body{};
     size_t tsz = 4, out_bytes = 0;
@@ -265,6 +266,7 @@ void lbm_default_adjoint_opts(lbm_adjoint_opts* o) {
     o->checkpoint_every = 100;
     o->weight_fx = 1.0;
     o->weight_fy = 0.0;
+    o->use_graphs = 1;
 }
 
 const char* lbm_adjoint_last_error(const lbm_adjoint* A) {
@@ -312,6 +314,7 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     A->nseg = (int)(N / K);
     A->wx = aopts->weight_fx;
     A->wy = aopts->weight_fy;
+    A->graphs = aopts->use_graphs != 0;
     A->body = *body;
     A->tsz = elem_size(o.storage);
     A->out_bytes = 3 * (size_t)ny * A->tsz;
@@ -385,7 +388,7 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     set_pose(A);
     rc = upload_ad(A);
     if (rc) return bail(rc);
-    if (K <= 1024) {
+    if (A->graphs && K <= 1024) {
         rc = lbm_set_graph_steps(s, K);
         if (rc) return A->err = s->err, bail(rc);
     }
@@ -512,6 +515,15 @@ int lbm_adjoint_backward(lbm_adjoint* A) {
     const int last = A->nseg - 1;
     AHIP_TRY(A, hipMemcpyAsync(A->seg_index, &last, sizeof(int), hipMemcpyHostToDevice, s->stream));
     AHIP_TRY(A, hipStreamSynchronize(s->stream));
+    if (!A->graphs) {
+        for (int k = 0; k < A->nseg; ++k) {
+            rc = enqueue_segment(A);
+            if (rc) return rc;
+        }
+        AHIP_TRY(A, hipStreamSynchronize(s->stream));
+        A->bwd_done = true;
+        return LBM_OK;
+    }
     if (!A->gexec) {
         AHIP_TRY(A, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
         rc = enqueue_segment(A);

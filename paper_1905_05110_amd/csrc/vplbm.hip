@@ -207,8 +207,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     // Launch configuration defaults (lbm_autotune refines them): two rows per lane for
     // grids up to 2.5 M nodes with FP32 arithmetic, one otherwise; nontemporal stores once
     // the two population buffers exceed 1 GiB (far beyond the 256 MB Infinity Cache).
-    s->rows = o.rows_per_tile ? o.rows_per_tile
-                              : ((o.storage != LBM_FP64 && (long long)nx * ny <= 2500000) ? 2 : 1);
+    s->rows = o.rows_per_tile ? o.rows_per_tile : 1;
     s->nt = o.store_mode == LBM_STORE_NONTEMPORAL ||
             (o.store_mode == LBM_STORE_AUTO && 2 * s->pop_bytes > (size_t(1) << 30));
     const int tiles_x = (nx + TILE_X - 1) / TILE_X;
@@ -999,8 +998,7 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
         nodes += (long long)s->nx * s->ny;
         bytes += s->pop_bytes;
     }
-    b->rows = bo.rows_per_tile ? bo.rows_per_tile
-                               : ((bo.storage != LBM_FP64 && nodes <= 2500000) ? 2 : 1);
+    b->rows = bo.rows_per_tile ? bo.rows_per_tile : 1;
     b->nt = bo.store_mode == LBM_STORE_NONTEMPORAL ||
             (bo.store_mode == LBM_STORE_AUTO && 2 * bytes > (size_t(1) << 30));
     for (lbm_sim* s : b->sims) {

@@ -110,16 +110,13 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         const double usx_d = a.pose[3] - a.pose[5] * ryg;
         const double usy_d = a.pose[4] + a.pose[5] * rxg;
         const T usx = (T)usx_d, usy = (T)usy_d;
-        // 3. forward node quantities
-        NodeOut<T> o;
-        macros<T, true>(c, g, (T)chi, (T)(usx_d - d.u0x), (T)(usy_d - d.u0y), o);
-        const T rho = o.rho, ux = o.ux, uy = o.uy, Gx = o.Gx, Gy = o.Gy;
-        const T rx = o.dux - (T)(usx_d - d.u0x), ry = o.duy - (T)(usy_d - d.u0y);
-        const T lam = (T)chi * c.inv_eta;
-        // 4. adjoint of the post-collision populations: transpose of the next pull
+        // 3. adjoint of the post-collision populations: transpose of the next pull (issued
+        // before the arithmetic below, so that both sets of loads are in flight together)
         T w[NQ];
         const unsigned row = (unsigned)d.pitch;
         const unsigned o0 = (unsigned)j * row + (unsigned)i;
+        T* chib = reinterpret_cast<T*>(a.chibar) + o0;
+        const T chib_old = gld(chib);
         if (inner) {
 #pragma unroll
             for (int b = 0; b < NQ; ++b)
@@ -138,6 +135,12 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
                 w[b] = acc;
             }
         }
+        // 4. forward node quantities
+        NodeOut<T> o;
+        macros<T, true>(c, g, (T)chi, (T)(usx_d - d.u0x), (T)(usy_d - d.u0y), o);
+        const T rho = o.rho, ux = o.ux, uy = o.uy, Gx = o.Gx, Gy = o.Gy;
+        const T rx = o.dux - (T)(usx_d - d.u0x), ry = o.duy - (T)(usy_d - d.u0y);
+        const T lam = (T)chi * c.inv_eta;
         // 5. reverse of the collision.  mbar* = M^-T w = diag(1/|row|^2) M w
         const T s1234 = (w[1] + w[2]) + (w[3] + w[4]);
         const T s5678 = (w[5] + w[6]) + (w[7] + w[8]);
@@ -216,8 +219,7 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         }
 #pragma unroll
         for (int b = 0; b < NQ; ++b) gst(Aout + (long long)b * ps + o0, pb[b]);
-        T* chib = reinterpret_cast<T*>(a.chibar) + o0;
-        gst(chib, gld(chib) + lamb * c.inv_eta);
+        gst(chib, chib_old + lamb * c.inv_eta);
         if (chi > 0.0) {  // where chi = 0 the step does not depend on u_s
             usum[0] = (double)usbx;
             usum[1] = (double)usby;

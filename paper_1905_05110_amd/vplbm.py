@@ -79,7 +79,7 @@ class BatchOpts(C.Structure):
 
 class AdjointOpts(C.Structure):
     _fields_ = [("steps", C.c_int64), ("checkpoint_every", C.c_int), ("weight_fx", C.c_double),
-                ("weight_fy", C.c_double)]
+                ("weight_fy", C.c_double), ("use_graphs", C.c_int)]
 
 
 RECORD_DTYPE = np.dtype([("step", "<i8"), ("fvp", "<f8", (2,)), ("tvp", "<f8"),
@@ -458,7 +458,8 @@ class Adjoint:
     ``backward()`` sweeps them in reverse, ``gradient()`` returns dJ/dchi [ny, nx],
     dJ/d(X, Y) and dJ/d(V_x, V_y, Omega)."""
 
-    def __init__(self, spec, body, steps, checkpoint_every=100, weights=(1.0, 0.0)):
+    def __init__(self, spec, body, steps, checkpoint_every=100, weights=(1.0, 0.0),
+                 graphs=True):
         L = load_library()
         self.L, self.h = L, None
         self.nx, self.ny = int(spec["nx"]), int(spec["ny"])
@@ -469,6 +470,7 @@ class Adjoint:
         L.lbm_default_adjoint_opts(C.byref(ao))
         ao.steps, ao.checkpoint_every = int(steps), int(checkpoint_every)
         ao.weight_fx, ao.weight_fy = float(weights[0]), float(weights[1])
+        ao.use_graphs = 1 if graphs else 0
         self.steps = int(steps)
         h = C.c_void_p()
         rc = L.lbm_adjoint_create(self.nx, self.ny, Rates(*[float(x) for x in spec["rates"]]),

@@ -166,7 +166,7 @@ def test_invalid_adjoint_arguments_are_rejected(lib, kw, frag):
 
 
 def test_adjoint_null_handles_and_layout(lib):
-    assert C.sizeof(vplbm.AdjointOpts) == 8 + 8 + 8 + 8
+    assert C.sizeof(vplbm.AdjointOpts) == 8 + 8 + 8 + 8 + 8
     J = C.c_double()
     assert lib.lbm_adjoint_forward(None, C.byref(J)) == vplbm.LBM_ERR_ARG
     assert lib.lbm_adjoint_backward(None) == vplbm.LBM_ERR_ARG

@@ -214,3 +214,19 @@ def test_full_size_fp32_against_fp64(gpu):
     assert (np.abs(np.array(fd) - g64["pos"]) <= bound).all(), (fd, g64["pos"], bound)
     a64.close()
     a32.close()
+
+
+def test_eager_and_graph_runs_agree(gpu):
+    spec, body = tiny("mixed")
+    f0 = W.random_populations(13, 11, seed=9, amp=0.05)
+    out = []
+    for graphs in (True, False):
+        adj = gpu.Adjoint(spec, body, 8, 4, (1.0, 0.3), graphs=graphs)
+        adj.set_initial(f0)
+        J = adj.forward()
+        adj.backward()
+        out.append((J, adj.gradient()))
+        adj.close()
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1]["chi"], out[1][1]["chi"])
+    assert np.array_equal(out[0][1]["pos"], out[1][1]["pos"])
