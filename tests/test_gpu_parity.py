@@ -160,6 +160,35 @@ def test_tiny_grids_step_by_step_reduced(gpu, storage, bcname, bodykind):
     g.close()
 
 
+@pytest.mark.parametrize("storage", ["fp16", "bf16", "fp32"])
+@pytest.mark.parametrize("bcname", ["channel", "periodic", "wallbox"])
+@pytest.mark.parametrize("rows", [1, 2])
+def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows):
+    """601 x 40 (three 256-column tiles, the last ragged and of odd width), free body
+    across a tile border: one step at a time from the stored state, against the oracle.
+    16-bit storage moves node pairs as 32-bit words with lane shifts in interior waves."""
+    from oracle import oracle as orc
+    nx, ny = 601, 40
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04, storage=storage,
+                   g=(2e-5, -1e-5) if bcname == "periodic" else (0.0, 0.0))
+    spec["rows_per_tile"] = rows
+    b = W.fixed_disc(14.0, 255.6, 19.3)
+    b.update(mode="free", free_mask=7, mass=300.0, inertia=2000.0, k=(0.01, 0.01, 0.0),
+             q0=(255.6, 19.3, 0.0))
+    tol = {"fp32": 2e-7, "fp16": 5e-5, "bf16": 5e-4}[storage]
+    g = gpu.Sim(spec, b)
+    o = orc.OracleSim(spec, b)
+    g.set_populations(W.random_populations(nx, ny, seed=21, amp=0.05))
+    for s in range(3):
+        fs = g.get_populations()
+        o.set_populations(fs)
+        g.step(1)
+        o.step(1)
+        e = rel(g.get_populations(), o.get_populations())
+        assert e <= tol, (s, e)
+    g.close()
+
+
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
 def test_several_tiles_and_ragged_tail_fp64(gpu, bcname):
     """nx = 600 spans three 256-wide tiles, the last one ragged; the body straddles
