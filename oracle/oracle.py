@@ -9,8 +9,8 @@ keys only; no code is shared):
 * ``spec``: ``nx, ny, rates=(s_e, s_eps, s_q, s_nu), eta, bc=(west, east, south,
   north), u_wall (4x2), u_conv, g_fluid (2), rho0, u0 (2)``;
 * ``body``: ``radius, x, y, theta, vx, vy, omega, mode, free_mask, mass, inertia,
-  k, c, q0, f_ext (3 each), imp_amp, imp_freq, imp_y0, smooth_delta,
-  internal_mass_correction``.
+  k, c, q0, f_ext (3 each), imp_amp, imp_freq, imp_y0, imp_phase, smooth_delta,
+  internal_mass_correction, force_model`` (``"vp"`` or ``"mem"``).
 
 The relaxation matrix follows the paper's choice for the conserved moments
 (Sec. 3, Eq. (28): s_0 = s_3 = s_5 = 1/tau = s_nu); the other rates come from the
@@ -25,6 +25,7 @@ from . import build as _build
 
 BC = {"periodic": 0, "wall": 1, "velocity": 2, "symmetry": 3, "outflow": 4}
 MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
+FORCE = {"vp": 0, "mem": 1}
 
 
 class Params(C.Structure):
@@ -45,7 +46,9 @@ class Params(C.Structure):
         ("k", C.c_double * 3), ("c", C.c_double * 3), ("q0", C.c_double * 3),
         ("f_ext", C.c_double * 3),
         ("imp_amp", C.c_double), ("imp_freq", C.c_double), ("imp_y0", C.c_double),
+        ("imp_phase", C.c_double),
         ("internal_mass_correction", C.c_int),
+        ("force_model", C.c_int),
         ("chi_add", C.c_void_p),
     ]
 
@@ -57,7 +60,8 @@ class Body(C.Structure):
 
 RECORD_DTYPE = np.dtype([("step", "<i8"), ("fvp", "<f8", (2,)), ("tvp", "<f8"),
                          ("pin", "<f8", (3,)), ("fh", "<f8", (2,)), ("th", "<f8"),
-                         ("q", "<f8", (3,)), ("v", "<f8", (3,))])
+                         ("q", "<f8", (3,)), ("v", "<f8", (3,)),
+                         ("fmem", "<f8", (2,)), ("tmem", "<f8")])
 
 _LIB = None
 _DP = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -89,6 +93,9 @@ def lib():
         L.orc_init.argtypes = [P, _DP, _DP, C.c_double, C.c_double, C.c_double]
         L.orc_fields.argtypes = [P, _DP, _DP, B, _DP, _DP, _DP]
         L.orc_pull_node.argtypes = [P, _DP, _DP, C.c_int, C.c_int, _DP]
+        L.orc_mem_node.argtypes = [P, B, C.c_int, C.c_int, _DP, _DP]
+        L.orc_link_point.argtypes = [P, B, C.c_int, C.c_int, C.c_int] + \
+            [C.POINTER(C.c_double)] * 2
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         _LIB = L
@@ -171,7 +178,10 @@ def make_params(spec, body=None, conserved=None) -> Params:
         p.imp_amp = float(body.get("imp_amp", 0.0))
         p.imp_freq = float(body.get("imp_freq", 0.0))
         p.imp_y0 = float(body.get("imp_y0", body.get("y", 0.0)))
+        p.imp_phase = float(body.get("imp_phase", 0.0))
         p.internal_mass_correction = int(body.get("internal_mass_correction", 1))
+        fm = body.get("force_model", "vp")
+        p.force_model = FORCE[fm] if isinstance(fm, str) else int(fm)
     return p
 
 
@@ -247,6 +257,21 @@ class OracleSim:
 
     def body_state(self):
         return np.array(self.b.q[:]), np.array(self.b.v[:])
+
+    def mem_node(self, i, j, out):
+        """Momentum-exchange contribution (Fx, Fy, T) of node (i, j) whose post-collision
+        populations are ``out`` (9 values), at the current pose."""
+        F = np.zeros(3)
+        lib().orc_mem_node(C.byref(self.p), C.byref(self.b), int(i), int(j),
+                           np.ascontiguousarray(out, dtype=np.float64), F)
+        return F
+
+    def link_point(self, i, j, a):
+        """Crossing of the circle by the link from fluid node (i, j) along c_a."""
+        x, y = C.c_double(), C.c_double()
+        lib().orc_link_point(C.byref(self.p), C.byref(self.b), int(i), int(j), int(a),
+                             C.byref(x), C.byref(y))
+        return x.value, y.value
 
     def chi_field(self):
         """Characteristic function and solid velocity at the current pose."""

@@ -15,9 +15,11 @@
  *   - streaming (applied as a pull) ..................... Sec. 2.2, Eq. (18)
  *   - implicit penalized velocity ....................... Sec. 2.2, Eqs. (19)-(22)
  *   - rigid-body equations, 4th-order Runge-Kutta ....... Sec. 2.3, Eqs. (23), (24), Algorithm 1
- *   - imposed transverse motion (sine form) ............. Sec. 3.1, Eq. (29) (shape only)
- * The fluid force on the body is the volume integral of the penalization force
- * (rho*chi/eta*(u - u_s)) rather than the momentum-exchange sum of Eqs. (25)-(27).
+ *   - imposed transverse motion, y0 + A sin(2 pi f t + phi) .. Sec. 3.1, Eq. (29)
+ *   - momentum-exchange force and torque ................ Sec. 2.3, Eqs. (25)-(27)
+ * The body is driven either by the volume integral of the penalization force
+ * (rho*chi/eta*(u - u_s), with the internal-fluid momentum term) or by the
+ * momentum-exchange sum of Eqs. (25)-(27); both are recorded at every step.
  *
  * Every 9x9 product is a plain double loop; there is no blocking, fusion or
  * reordering.  Compile with -O2 -ffp-contract=off (no -ffast-math).
@@ -53,6 +55,7 @@ static const double MM[Q][Q] = {
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_SYMMETRY = 3, BC_OUTFLOW = 4 };
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum { MODE_FIXED = 0, MODE_IMPOSED_SIN = 1, MODE_FREE = 2, MODE_CONST_VEL = 3 };
+enum { FORCE_VP = 0, FORCE_MEM = 1 };
 
 typedef struct {
     int nx, ny;
@@ -70,8 +73,9 @@ typedef struct {
     unsigned free_mask;   /* bit 0: x, bit 1: y, bit 2: theta */
     double mass, inertia;
     double k[3], c[3], q0[3], f_ext[3];
-    double imp_amp, imp_freq, imp_y0;
+    double imp_amp, imp_freq, imp_y0, imp_phase;
     int internal_mass_correction;
+    int force_model;      /* FORCE_VP or FORCE_MEM: the load that drives a FREE body */
     /* optional [ny][nx] field added to the indicator (NULL: none); the design variable
      * of the sensitivity checks, perturbed node by node for finite differences */
     const double* chi_add;
@@ -92,6 +96,7 @@ typedef struct {
                              inside the body: sum of chi * (j + G) and chi * r x (j + G) */
     double fh[2], th;     /* hydrodynamic force/torque (with the internal-fluid term when enabled) */
     double q[3], v[3];    /* pose and velocities used during this step */
+    double fmem[2], tmem; /* momentum-exchange force and torque, Eqs. (25)-(27) */
 } orc_record;
 
 /* ---- small helpers ------------------------------------------------------------- */
@@ -240,6 +245,66 @@ void orc_node(const orc_params* p, const double* P, double chi, double usx, doub
     }
 }
 
+/* ---- momentum-exchange force (Sec. 2.3, Eqs. (25)-(27)) ------------------------ */
+static int opposite(int a);
+
+/* A node is solid when it lies in the closed disc, d^2 <= R^2 (the sharp indicator of
+ * Eq. (2); the same classification is used when chi is smoothed). */
+static int solid_node(const orc_params* p, const orc_body* b, int i, int j) {
+    double dx = (double)i - b->q[0];
+    double dy = (double)j - b->q[1];
+    return dx * dx + dy * dy <= p->radius * p->radius;
+}
+
+/* Point x_Gamma where the link from fluid node (fi, fj) along c_a (towards a solid
+ * node) crosses the circle: x_f + q c_a with |x_f + q c_a - x_G| = R, the root of
+ * |c_a|^2 q^2 + 2 (c_a . d) q + |d|^2 - R^2 = 0 (d = x_f - x_G) nearest x_f. */
+void orc_link_point(const orc_params* p, const orc_body* b, int fi, int fj, int a, double* xg,
+                    double* yg) {
+    double dx = (double)fi - b->q[0];
+    double dy = (double)fj - b->q[1];
+    double A = (double)(CX[a] * CX[a] + CY[a] * CY[a]);
+    double Bh = CX[a] * dx + CY[a] * dy;
+    double Cc = dx * dx + dy * dy - p->radius * p->radius;
+    double q = (-Bh - sqrt(Bh * Bh - A * Cc)) / A;
+    *xg = (double)fi + q * CX[a];
+    *yg = (double)fj + q * CY[a];
+}
+
+/* Contribution of node (i, j), with post-collision populations out[], to the
+ * momentum-exchange force F[0..1] and torque F[2] on the body.  A link joins a fluid
+ * node x_f to the solid node x_s = x_f + e_alpha; on it the force of Eq. (25) is
+ * (e_alpha - u_Gamma) f~_alpha(x_f) - (e_alphabar - u_Gamma) f~_alphabar(x_s), with
+ * u_Gamma the rigid-body velocity at x_Gamma; Eq. (27) takes its moment about x_G.
+ * Each end of a link adds its own term: the fluid node the first, the solid node the
+ * second (its population along the link, back towards x_f). */
+void orc_mem_node(const orc_params* p, const orc_body* b, int i, int j, const double* out,
+                  double* F) {
+    F[0] = F[1] = F[2] = 0.0;
+    if (!p->has_body) return;
+    int self_solid = solid_node(p, b, i, j);
+    for (int a = 1; a < Q; ++a) {
+        int ni = i + CX[a], nj = j + CY[a];
+        if (solid_node(p, b, ni, nj) == self_solid) continue;
+        double xg, yg, sgn;
+        if (!self_solid) { /* this node is x_f, e_alpha = c_a */
+            orc_link_point(p, b, i, j, a, &xg, &yg);
+            sgn = 1.0;
+        } else { /* this node is x_s; x_f = (ni, nj), e_alpha = -c_a, alphabar = a */
+            orc_link_point(p, b, ni, nj, opposite(a), &xg, &yg);
+            sgn = -1.0;
+        }
+        double rgx = xg - b->q[0], rgy = yg - b->q[1];
+        double ugx = b->v[0] - b->v[2] * rgy;
+        double ugy = b->v[1] + b->v[2] * rgx;
+        double fx = sgn * (CX[a] - ugx) * out[a];
+        double fy = sgn * (CY[a] - ugy) * out[a];
+        F[0] += fx;
+        F[1] += fy;
+        F[2] += rgx * fy - rgy * fx;
+    }
+}
+
 /* ---- streaming with boundary rules (Eq. (18) as a pull; Sec. 3.1 boundaries) ---- */
 static int flip_x(int a) {
     for (int b = 0; b < Q; ++b)
@@ -332,9 +397,10 @@ void orc_rk4(double Mq, double cq, double kq, double q0, double F, double* q, do
 
 static const double TWO_PI = 6.283185307179586476925286766559;
 
-/* Pose for the imposed motion y = y0 + A sin(2 pi f t). */
+/* Pose for the imposed motion y = y0 + A sin(2 pi f t + phi); phi = pi/2 gives the
+ * cosine law of Eq. (29) with y0 = y_G(0) - A. */
 static void imposed_pose(const orc_params* p, orc_body* b) {
-    double ph = TWO_PI * p->imp_freq * (double)b->t_body;
+    double ph = TWO_PI * p->imp_freq * (double)b->t_body + p->imp_phase;
     b->q[1] = p->imp_y0 + p->imp_amp * sin(ph);
     b->v[1] = TWO_PI * p->imp_freq * p->imp_amp * cos(ph);
 }
@@ -381,14 +447,14 @@ void orc_body_advance(const orc_params* p, orc_body* b, const double* F) {
 int orc_step(const orc_params* p, const double* fin, double* fout, double* outlet, orc_body* b,
              orc_record* rec, int64_t step) {
     const int nx = p->nx, ny = p->ny;
-    double* rows = (double*)calloc((size_t)ny * 9, sizeof(double));
+    double* rows = (double*)calloc((size_t)ny * 12, sizeof(double));
     double* new_out = (double*)calloc((size_t)3 * ny, sizeof(double));
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j < ny; ++j) {
-        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int i = 0; i < nx; ++i) {
-            double P[Q], out[Q], rho, ux, uy, G[2], dF[2], chi, usx, usy;
+            double P[Q], out[Q], rho, ux, uy, G[2], dF[2], chi, usx, usy, Fm[3];
             double jx = 0.0, jy = 0.0;
             for (int a = 0; a < Q; ++a) P[a] = pull(p, fin, outlet, a, i, j);
             for (int a = 0; a < Q; ++a) {
@@ -416,14 +482,18 @@ int orc_step(const orc_params* p, const double* fin, double* fout, double* outle
             acc[6] += chi * jx;
             acc[7] += chi * jy;
             acc[8] += chi * (rx * jy - ry * jx);
+            orc_mem_node(p, b, i, j, out, Fm);
+            acc[9] += Fm[0];
+            acc[10] += Fm[1];
+            acc[11] += Fm[2];
             (void)ux;
             (void)uy;
         }
-        for (int k = 0; k < 9; ++k) rows[(size_t)j * 9 + k] = acc[k];
+        for (int k = 0; k < 12; ++k) rows[(size_t)j * 12 + k] = acc[k];
     }
-    double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double tot[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int j = 0; j < ny; ++j)
-        for (int k = 0; k < 9; ++k) tot[k] += rows[(size_t)j * 9 + k];
+        for (int k = 0; k < 12; ++k) tot[k] += rows[(size_t)j * 12 + k];
     if (p->bc[SIDE_E] == BC_OUTFLOW) memcpy(outlet, new_out, sizeof(double) * 3 * (size_t)ny);
     free(rows);
     free(new_out);
@@ -453,9 +523,17 @@ int orc_step(const orc_params* p, const double* fin, double* fout, double* outle
         r.v[d] = b->v[d];
         b->pin_prev[d] = r.pin[d];
     }
+    r.fmem[0] = tot[9];
+    r.fmem[1] = tot[10];
+    r.tmem = tot[11];
     b->pin_valid = 1;
     if (rec) *rec = r;
     double F[3] = {r.fh[0], r.fh[1], r.th};
+    if (p->force_model == FORCE_MEM) {
+        F[0] = r.fmem[0];
+        F[1] = r.fmem[1];
+        F[2] = r.tmem;
+    }
     if (p->has_body) orc_body_advance(p, b, F);
     return bad;
 }
