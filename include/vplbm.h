@@ -94,6 +94,14 @@ enum { LBM_WEST = 0, LBM_EAST = 1, LBM_SOUTH = 2, LBM_NORTH = 3 };
  * advances by its constant velocities every step. */
 enum { LBM_BODY_FIXED = 0, LBM_BODY_IMPOSED_SIN = 1, LBM_BODY_FREE = 2, LBM_BODY_CONST_VEL = 3 };
 
+/* Load that drives a FREE body, and whether the momentum-exchange sum of Sec. 2.3,
+ * Eqs. (25)-(27) is evaluated (it costs a pass over the body's tiles every step):
+ *   LBM_FORCE_VP      the penalization force with the internal-momentum term (fh);
+ *                     fmem and tmem are recorded as 0
+ *   LBM_FORCE_MEM     the momentum-exchange force and torque (fmem, tmem)
+ *   LBM_FORCE_VP_MEM  fh drives the body; fmem and tmem are recorded alongside */
+enum { LBM_FORCE_VP = 0, LBM_FORCE_MEM = 1, LBM_FORCE_VP_MEM = 2 };
+
 /* MRT relaxation rates of the non-conserved moments (Sec. 2.2, Eq. (16)):
  * s_e (energy), s_eps (energy square), s_q (heat fluxes), s_nu (stresses; 1/tau,
  * nu = (tau - 1/2)/3 by Eq. (6)).  Each must lie in (0, 2).  The rates of the
@@ -128,12 +136,16 @@ typedef struct {
     unsigned free_mask;                        /* FREE: bit 0 x, bit 1 y, bit 2 theta */
     double mass, inertia;                      /* m and I of Eqs. (23)-(24) */
     double k[3], c[3], q0[3], f_ext[3];        /* stiffness, damping, rest pose, external load */
-    double imp_amp, imp_freq, imp_y0;          /* IMPOSED_SIN parameters */
+    double imp_amp, imp_freq, imp_y0;          /* IMPOSED_SIN: y = y0 + A sin(2 pi f t + phase),
+                                                  t in steps since lbm_set_body; phase =
+                                                  pi/2 gives the cosine law of Eq. (29) */
     double smooth_delta;                       /* 0: sharp chi (d^2 <= R^2); > 0: chi =
                                                   1/(1 + exp(2 (d - R)/delta)), 0 beyond
                                                   d - R > 20 delta, 1 below -20 delta */
     int internal_mass_correction;              /* 1: fh includes the internal-momentum
                                                   change (see lbm_force_rec) */
+    double imp_phase;                          /* IMPOSED_SIN phase (radians) */
+    int force_model;                           /* LBM_FORCE_* (default LBM_FORCE_VP) */
 } lbm_body;
 
 /* Per-step record, written on the device for every step. */
@@ -150,6 +162,13 @@ typedef struct {
                           first step after lbm_set_body, pin(n-1) is the pre-collision
                           momentum inside the body, sum chi j. */
     double q[3], v[3]; /* pose (x, y, theta) and velocities during this step */
+    double fmem[2];    /* (LBM_FORCE_MEM, LBM_FORCE_VP_MEM; else 0) momentum-exchange
+                          force of Eqs. (25)-(27): over the links from a
+                          fluid node x_f to a solid node x_s = x_f + c_a (solid: d^2 <= R^2,
+                          whatever the indicator mode), (c_a - u_G) f~_a(x_f) - (-c_a - u_G)
+                          f~_abar(x_s), with x_G the crossing of the link and the circle
+                          and u_G the rigid velocity there (post-collision populations) */
+    double tmem;       /* its torque about the body centre, sum (x_G - X) x F */
 } lbm_force_rec;
 
 /* Fills o with defaults: periodic on all sides, rho0 = 1, u0 = 0, FP32 storage. */

@@ -10,7 +10,8 @@ keys only; no code is shared):
   north), u_wall (4x2), u_conv, g_fluid (2), rho0, u0 (2)``;
 * ``body``: ``radius, x, y, theta, vx, vy, omega, mode, free_mask, mass, inertia,
   k, c, q0, f_ext (3 each), imp_amp, imp_freq, imp_y0, imp_phase, smooth_delta,
-  internal_mass_correction, force_model`` (``"vp"`` or ``"mem"``).
+  internal_mass_correction, force_model`` (``"vp"``, ``"mem"`` or ``"vp+mem"``: the load
+  that drives a free body is the momentum exchange for ``"mem"`` only).
 
 The relaxation matrix follows the paper's choice for the conserved moments
 (Sec. 3, Eq. (28): s_0 = s_3 = s_5 = 1/tau = s_nu); the other rates come from the
@@ -25,7 +26,7 @@ from . import build as _build
 
 BC = {"periodic": 0, "wall": 1, "velocity": 2, "symmetry": 3, "outflow": 4}
 MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
-FORCE = {"vp": 0, "mem": 1}
+FORCE = {"vp": 0, "mem": 1, "vp+mem": 2}  # the oracle evaluates both loads always
 
 
 class Params(C.Structure):

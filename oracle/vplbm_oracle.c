@@ -55,7 +55,7 @@ static const double MM[Q][Q] = {
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_SYMMETRY = 3, BC_OUTFLOW = 4 };
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum { MODE_FIXED = 0, MODE_IMPOSED_SIN = 1, MODE_FREE = 2, MODE_CONST_VEL = 3 };
-enum { FORCE_VP = 0, FORCE_MEM = 1 };
+enum { FORCE_VP = 0, FORCE_MEM = 1, FORCE_VP_WITH_MEM = 2 };
 
 typedef struct {
     int nx, ny;
@@ -75,7 +75,8 @@ typedef struct {
     double k[3], c[3], q0[3], f_ext[3];
     double imp_amp, imp_freq, imp_y0, imp_phase;
     int internal_mass_correction;
-    int force_model;      /* FORCE_VP or FORCE_MEM: the load that drives a FREE body */
+    int force_model;      /* FORCE_MEM: the exchange load drives a FREE body; else the
+                             penalization load (both are always recorded here) */
     /* optional [ny][nx] field added to the indicator (NULL: none); the design variable
      * of the sensitivity checks, perturbed node by node for finite differences */
     const double* chi_add;

@@ -360,6 +360,9 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
         return fail(s, LBM_ERR_ARG, "FREE bodies need mass > 0 and inertia > 0");
     if (!(b->smooth_delta >= 0.0)) return fail(s, LBM_ERR_ARG, "smooth_delta must be >= 0");
     if (b->free_mask > 7u) return fail(s, LBM_ERR_ARG, "free_mask has bits beyond x, y, theta");
+    if (b->force_model < LBM_FORCE_VP || b->force_model > LBM_FORCE_VP_MEM)
+        return fail(s, LBM_ERR_ARG, "force_model must be LBM_FORCE_VP, _MEM or _VP_MEM");
+    if (!std::isfinite(b->imp_phase)) return fail(s, LBM_ERR_ARG, "non-finite imp_phase");
     const double vals[] = {b->x, b->y, b->theta, b->vx, b->vy, b->omega};
     for (double x : vals)
         if (!std::isfinite(x)) return fail(s, LBM_ERR_ARG, "non-finite pose or velocity");
@@ -371,6 +374,7 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     B.mode = b->mode;
     B.free_mask = b->free_mask;
     B.imc = b->internal_mass_correction ? 1 : 0;
+    B.mem = b->force_model == LBM_FORCE_MEM ? 1 : (b->force_model == LBM_FORCE_VP_MEM ? 2 : 0);
     B.smooth = b->smooth_delta > 0.0;
     B.R = b->radius;
     B.R2 = b->radius * b->radius;
@@ -387,11 +391,12 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     B.amp = b->imp_amp;
     B.freq = b->imp_freq;
     B.y0 = b->imp_y0;
+    B.phase = b->imp_phase;
     const int p = (int)(s->host_step & 1);
     double q[3] = {b->x, b->y, b->theta}, v[3] = {b->vx, b->vy, b->omega};
     if (b->mode == LBM_BODY_IMPOSED_SIN) {
-        q[1] = b->imp_y0;  // sin(0) = 0
-        v[1] = 6.283185307179586476925286766559 * b->imp_freq * b->imp_amp;
+        q[1] = b->imp_y0 + b->imp_amp * std::sin(b->imp_phase);
+        v[1] = 6.283185307179586476925286766559 * b->imp_freq * b->imp_amp * std::cos(b->imp_phase);
     }
     BodyState& st = B.st[p];
     for (int k = 0; k < 3; ++k) {

@@ -19,8 +19,9 @@ constexpr int NQ = 9;
 constexpr int TILE_X = 256;  // columns of a tile: one per lane of a 256-thread workgroup
 constexpr int NWAVE = TILE_X / 64;
 // per-step FP64 sums: penalization force (2) and torque (1); momentum inside the body
-// after collision (2 + 1 angular) and before it (2 + 1)
-constexpr int NRED = 9;
+// after collision (2 + 1 angular) and before it (2 + 1); momentum-exchange force (2)
+// and torque (1)
+constexpr int NRED = 12;
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_SYMMETRY = 3, BC_OUTFLOW = 4 };
 enum { MODE_FIXED = 0, MODE_IMPOSED_SIN = 1, MODE_FREE = 2, MODE_CONST_VEL = 3 };
@@ -79,11 +80,13 @@ struct BodyDev {
     int active, mode;
     unsigned free_mask;
     int imc;  // internal-fluid momentum correction for FREE bodies
-    int smooth, pad0;
+    int smooth;
+    int mem;  // momentum-exchange sum: 0 not evaluated, 1 evaluated and drives FREE bodies,
+              // 2 evaluated and recorded only
     double R, R2, delta, reach;
     double mass, inertia;
     double k[3], c[3], q0[3], fext[3];
-    double amp, freq, y0;
+    double amp, freq, y0, phase;
     // State of step n in st[n & 1].  Step n's kernel derives it from st[(n - 1) & 1] and
     // the partial sums of step n - 1 (every tile that needs it, identically) unless the
     // host or a flush already wrote it ("fresh").
@@ -92,7 +95,7 @@ struct BodyDev {
 
 struct Record {  // same layout as lbm_force_rec
     long long step;
-    double fvp[2], tvp, pin[3], fh[2], th, q[3], v[3];
+    double fvp[2], tvp, pin[3], fh[2], th, q[3], v[3], fmem[2], tmem;
 };
 
 // Per-simulation constants in the arithmetic precision T, precomputed on the host.
@@ -604,7 +607,7 @@ __device__ __forceinline__ void rk4_dof(double Mq, double cq, double kq, double 
 // Working set, in LDS, of the body update that ends a step.
 struct BodyStep {
     double tot[NRED];  // the step's FP64 sums
-    double F[3];       // load used by the body update (F_h x, y and T_h)
+    double F[3];       // penalization load F_h (x, y and T_h), recorded as fh
     double q[3], v[3]; // state of the next step
     long long step, t_body;
     int boxM[4];
@@ -709,8 +712,9 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
                 const BodyDev& B = *d.body;
                 double chi = 0.0, dsx = 0.0, dsy = 0.0;
                 const double rx = (double)i - pose[0], ry = (double)j - pose[1];
+                const double d2 = disc_d2(rx, ry);
                 if (B.active) {
-                    chi = disc_chi(B, disc_d2(rx, ry));
+                    chi = disc_chi(B, d2);
                     if (chi > 0.0) {
                         const double om = pose[5];
                         dsx = (pose[3] - om * ry) - d.u0x;
@@ -750,6 +754,67 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
             for (int a = 0; a < NQ; ++a) g[a] = gn[a];
         }
     }
+}
+
+// Momentum-exchange load (Sec. 2.3, Eqs. (25)-(27)) of a participating tile's lane,
+// m = (Fx, Fy, T), after the tile's rows are stored.  Solid nodes are those with d^2 <= R^2 (in both
+// indicator modes).  A link joins a fluid node x_f to the solid node x_s = x_f + e; its
+// force (e - u_G) f~_e(x_f) - (-e - u_G) f~_-e(x_s) is shared out as one term per end,
+// each end evaluating x_G (the crossing of the link and the circle, taken from the fluid
+// end so that both ends agree) and the rigid velocity u_G there.  A lane visits its
+// nodes within one lattice step of the circle and reads back the post-collision
+// populations it has just written along their links (the values that stream).  The
+// directions are walked one at a time, apart from the collision, so that this adds no
+// registers to it.
+template <class S, int ROWS>
+__device__ __forceinline__ void mem_pass(const SimDesc& d, int tx, int ty, int p,
+                                         const double* pose, double m[3]) {
+    const BodyDev& B = *d.body;
+    const int i = tx * TILE_X + (int)threadIdx.x;
+    m[0] = m[1] = m[2] = 0.0;
+    if (!B.active || !B.mem || i >= d.nx) return;
+    // uniform over the workgroup: kept in scalar registers
+    const double R2 = uniform_value(B.R2);
+    const double band = uniform_value(B.R + 1.5), inner = uniform_value(B.R - 1.5);
+    const double X = uniform_value(pose[0]), Y = uniform_value(pose[1]);
+    const double Vx = uniform_value(pose[3]), Vy = uniform_value(pose[4]);
+    const double Om = uniform_value(pose[5]);
+    double mx = 0.0, my = 0.0, mt = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < ROWS; ++r) {
+        const int j = ty * ROWS + r;
+        if (j >= d.ny) break;
+        const double rx = (double)i - X, ry = (double)j - Y;
+        const double d2 = disc_d2(rx, ry);
+        if (d2 > band * band || (inner > 0.0 && d2 < inner * inner)) continue;
+        const bool self_solid = d2 <= R2;
+        const unsigned off = node_off<S>(d, i, j);
+#pragma unroll 1
+        for (int a = 1; a < NQ; ++a) {
+            const int cx = dir_cx(a), cy = dir_cy(a);
+            const double nrx = (double)(i + cx) - X, nry = (double)(j + cy) - Y;
+            if ((disc_d2(nrx, nry) <= R2) == self_solid) continue;
+            const double f = d.fref[a] + (double)Codec<S>::load(plane<S>(d, d.pop[p ^ 1], a), off,
+                                                                 d.inv_scale);
+            // fluid end (relative to the centre) and link direction towards the solid
+            const double fx = self_solid ? nrx : rx, fy = self_solid ? nry : ry;
+            const double ex = self_solid ? -cx : cx, ey = self_solid ? -cy : cy;
+            // nearer root of |f + q e|^2 = R^2, written without cancellation (c > 0, b < 0)
+            const double qa = ex * ex + ey * ey, qb = ex * fx + ey * fy;
+            const double qc = fx * fx + fy * fy - R2;
+            const double q = qc / (-qb + sqrt(qb * qb - qa * qc));
+            const double gx = fx + q * ex, gy = fy + q * ey;  // x_G - X
+            const double ugx = Vx - Om * gy, ugy = Vy + Om * gx;
+            const double sg = self_solid ? -1.0 : 1.0;
+            const double Fx = sg * ((double)cx - ugx) * f, Fy = sg * ((double)cy - ugy) * f;
+            mx += Fx;
+            my += Fy;
+            mt += gx * Fy - gy * Fx;
+        }
+    }
+    m[0] = mx;
+    m[1] = my;
+    m[2] = mt;
 }
 
 // Fixed-order FP64 sum of a step's partial slots by one workgroup of TILE_X threads
@@ -804,14 +869,14 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
     if (k < 3) {
         double dp = 0.0;
         if (B.imc) dp = bs.tot[3 + k] - (pin_valid ? pin_prev : bs.tot[6 + k]);
-        const double F = bs.tot[k] + dp;
-        bs.F[k] = F;
+        bs.F[k] = bs.tot[k] + dp;
+        const double F = B.mem == 1 ? bs.tot[9 + k] : bs.F[k];
         double q = q_prev, v = v_prev;
         if (B.active) {
             if (B.mode == MODE_IMPOSED_SIN) {
                 if (k == 1) {
                     const double w = 6.283185307179586476925286766559 * B.freq;
-                    const double ph = w * (double)(t_prev + 1);
+                    const double ph = w * (double)(t_prev + 1) + B.phase;
                     q = B.y0 + B.amp * sin(ph);
                     v = w * B.amp * cos(ph);
                 }
@@ -848,6 +913,9 @@ __device__ __forceinline__ void write_record(const SimDesc& d, const BodyState& 
     r.fh[0] = bs.F[0];
     r.fh[1] = bs.F[1];
     r.th = bs.F[2];
+    r.fmem[0] = bs.tot[9];
+    r.fmem[1] = bs.tot[10];
+    r.tmem = bs.tot[11];
 }
 
 // State slot of step n from the derived update (one thread); fresh marks a flush.
@@ -924,9 +992,17 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < NRED; ++k) {
+    for (int k = 0; k < NRED - 3; ++k) {
         const double s = wave_sum(acc[k]);
         if (lane == 0) red[wave][k] = s;
+    }
+    // the momentum-exchange pass runs once the other sums have left the registers
+    double m[3];
+    mem_pass<S, ROWS>(d, tx, ty, p, pose, m);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double s = wave_sum(m[k]);
+        if (lane == 0) red[wave][NRED - 3 + k] = s;
     }
     __syncthreads();
     if (threadIdx.x < NRED) {

@@ -19,6 +19,7 @@ LBM_OK, LBM_ERR_ARG, LBM_ERR_ALLOC, LBM_ERR_HIP, LBM_ERR_UNSTABLE, LBM_ERR_STATE
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 BC = {"periodic": 0, "wall": 1, "velocity": 2, "symmetry": 3, "outflow": 4}
 MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
+FORCE = {"vp": 0, "mem": 1, "vp+mem": 2}  # driving load; "mem"/"vp+mem" evaluate the exchange sum
 STORE = {"auto": 0, "plain": 1, "nontemporal": 2}
 ORDER = {"given": 0, "largest_first": 1, "interleaved": 2}
 
@@ -64,7 +65,8 @@ class Body(C.Structure):
                 ("mass", C.c_double), ("inertia", C.c_double), ("k", C.c_double * 3),
                 ("c", C.c_double * 3), ("q0", C.c_double * 3), ("f_ext", C.c_double * 3),
                 ("imp_amp", C.c_double), ("imp_freq", C.c_double), ("imp_y0", C.c_double),
-                ("smooth_delta", C.c_double), ("internal_mass_correction", C.c_int)]
+                ("smooth_delta", C.c_double), ("internal_mass_correction", C.c_int),
+                ("imp_phase", C.c_double), ("force_model", C.c_int)]
 
 
 class BatchDesc(C.Structure):
@@ -84,7 +86,8 @@ class AdjointOpts(C.Structure):
 
 RECORD_DTYPE = np.dtype([("step", "<i8"), ("fvp", "<f8", (2,)), ("tvp", "<f8"),
                          ("pin", "<f8", (3,)), ("fh", "<f8", (2,)), ("th", "<f8"),
-                         ("q", "<f8", (3,)), ("v", "<f8", (3,))])
+                         ("q", "<f8", (3,)), ("v", "<f8", (3,)),
+                         ("fmem", "<f8", (2,)), ("tmem", "<f8")])
 
 _LIB = None
 _DP = C.POINTER(C.c_double)
@@ -210,6 +213,9 @@ def make_body(body):
     b.imp_y0 = float(body.get("imp_y0", body.get("y", 0.0)))
     b.smooth_delta = float(body.get("smooth_delta", 0.0))
     b.internal_mass_correction = int(body.get("internal_mass_correction", 1))
+    b.imp_phase = float(body.get("imp_phase", 0.0))
+    fm = body.get("force_model", "vp")
+    b.force_model = FORCE[fm] if isinstance(fm, str) else int(fm)
     return b
 
 

@@ -63,6 +63,27 @@ def imposed_oscillation(storage="fp64", nx=200, ny=80, D=20.0, U0=0.05, Re=100.0
                 U0=U0, D=D)
 
 
+def paper_imposed_oscillation(storage="fp64", nx=1230, ny=410, D=41.0, U0=0.04878,
+                              tau=0.56, omega_star=1.55, B_star=0.25, eta=1e-6):
+    """The paper's imposed-displacement case (Sec. 3.1): channel 1230 x 410, D = 41,
+    tau = 0.56 (Re = 100), U0 = 0.04878, rates (1.1, 1.25, 1.8) for (e, eps, q) with
+    the others 1/tau (Eq. (28)), eta = 1e-6, and after a fixed-cylinder run the law
+    y_G(t) = (y_G(0) - B) + B cos(omega t) of Eq. (29) with omega* = omega D / U0 = 1.55
+    and B* = B / D = 1/4.  The disc sits at (nx/4, ny/2).  Returns the fixed body of the
+    preliminary run and the moving one (cosine law: phase pi/2)."""
+    spec = channel_spec(nx, ny, U0, tau, eta=eta, storage=storage)
+    spec["rates"] = (1.1, 1.25, 1.8, 1.0 / tau)
+    x, y = nx / 4.0, ny / 2.0
+    fixed = fixed_disc(D, x, y)
+    fixed["force_model"] = "mem"
+    B = B_star * D
+    omega = omega_star * U0 / D
+    moving = dict(fixed, mode="imposed_sin", imp_amp=B, imp_freq=omega / (2.0 * math.pi),
+                  imp_y0=y - B, imp_phase=0.5 * math.pi)
+    return dict(name="paper_imposed_%dx%d" % (nx, ny), spec=spec, fixed=fixed, body=moving,
+                U0=U0, D=D, period=2.0 * math.pi / omega)
+
+
 def viv_body(D, x, y, U0, Ur, mass_ratio=10.0, damping=0.0):
     m = mass_ratio * math.pi * D * D / 4.0  # mass ratio x displaced fluid mass (rho0 = 1)
     fn = U0 / (Ur * D)
@@ -85,6 +106,40 @@ def confinement_kappa(Ht: float) -> float:
     """Wall-correction factor of the confined settling law (Sec. 3.2, Eq. (34))."""
     return 1.0 / (math.log(Ht) - 0.9157 + 1.7244 * Ht ** -2 - 1.7302 * Ht ** -4
                   + 2.4056 * Ht ** -6 - 4.5913 * Ht ** -8)
+
+
+PAPER_DENSITY_RATIOS = (0.95, 0.98, 0.99, 1.01, 1.02, 1.05)
+
+
+def paper_sedimentation_centered(rho_ratio, storage="fp64", D=24.0, Ht=5.0, L=1200,
+                                 tau=0.8, D_cm=0.24, mu=0.1, g_cm=980.0,
+                                 force_model="mem"):
+    """The paper's centred settling case (Sec. 3.2.1): a disc of D = 0.24 cm (24 nodes)
+    in a channel of width H = 5 D and length L = 1200 nodes, fluid rho = 1 g/cm^3,
+    mu = 0.1 g/(cm s), |g| = 980 cm/s^2, tau = 0.8, released at rest on the centre
+    line half-way along the channel.  Lattice units follow from dx = D_cm / D and
+    nu_lattice = (tau - 1/2)/3 = nu dt / dx^2.  The channel axis is x here (the D2Q9
+    lattice is symmetric under a quarter turn) with gravity along +x; both ends are
+    closed (the net flux through every section is zero, as with the zero-velocity top
+    and far outlet of the paper).  The disc is free in x, y and theta with
+    m = rho_s pi D^2 / 4, I = m R^2 / 2 and the load of Eq. (31): m (1 - rho/rho_s) g.
+    Returns also the confined settling velocity of Eqs. (32)-(34) in lattice units."""
+    H = int(round(Ht * D))
+    nu_l = (tau - 0.5) / 3.0
+    dx = D_cm / D
+    dt = nu_l * dx * dx / (mu / 1.0)
+    g = g_cm * dt * dt / dx
+    spec = dict(nx=int(L), ny=H, rates=rates_for_tau(tau), eta=ETA, bc=("wall",) * 4,
+                u_wall=[[0.0, 0.0]] * 4, u_conv=0.0, g_fluid=(0.0, 0.0), rho0=1.0,
+                u0=(0.0, 0.0), storage=storage)
+    m = rho_ratio * math.pi * D * D / 4.0
+    body = fixed_disc(D, L / 2.0, (H - 1) / 2.0)
+    body.update(mode="free", free_mask=0b111, mass=m, inertia=0.5 * m * (D / 2.0) ** 2,
+                f_ext=(m * (1.0 - 1.0 / rho_ratio) * g, 0.0, 0.0), force_model=force_model)
+    kappa = confinement_kappa(Ht)
+    vs = D * D * (rho_ratio - 1.0) * g / (16.0 * kappa * nu_l)  # along +x (mu = nu, rho = 1)
+    return dict(name="paper_sedimentation_%g" % rho_ratio, spec=spec, body=body, vs=vs,
+                g=g, dt=dt, dx=dx, kappa=kappa, D=D)
 
 
 def sedimentation(storage="fp32", nx=1024, ny=4096, D=32.0, x=512.0, y=3800.0, rho_ratio=1.5,

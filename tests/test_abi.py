@@ -34,8 +34,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    assert C.sizeof(vplbm.Body) == 8 * 7 + 4 + 4 + 8 * 2 + 8 * 12 + 8 * 4 + 8
-    assert vplbm.RECORD_DTYPE.itemsize == 128
+    assert C.sizeof(vplbm.Body) == 8 * 7 + 4 + 4 + 8 * 2 + 8 * 12 + 8 * 4 + 8 + 8 + 8
+    assert vplbm.RECORD_DTYPE.itemsize == 128 + 24
 
 
 def _create(lib, nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3, **kw):

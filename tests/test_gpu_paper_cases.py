@@ -1,0 +1,104 @@
+"""The paper's own configurations on the GPU path (Sec. 3.1 and Sec. 3.2.1), checked
+against the values the paper prints or the closed form it compares with.
+
+* Imposed transverse oscillation (Sec. 3.1, Table 1): 1230 x 410, D = 41, Re = 100,
+  omega* = 1.55, B* = 1/4.  The paper prints a mean drag coefficient of 1.653 from the
+  momentum-exchange force.  Reading: the flow past the fixed disc is first run to
+  periodic shedding (100 000 steps, t* = 119), then the motion starts; the mean is
+  taken over the whole periods up to t* = 64 (the time of the paper's field snapshots).
+* Centred settling (Sec. 3.2.1, Eqs. (32)-(34)): H/D = 5, D = 24, tau = 0.8, six density
+  ratios; the terminal velocity against the confined Stokes settling velocity.  The
+  paper finds agreement for rho_r in {0.98, 0.99, 1.01, 1.02} and a visible gap for
+  0.95 and 1.05 (Re = 3.2, beyond the Stokes regime of the closed form).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1905_05110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_05110_amd import vplbm
+    vplbm.load_library()
+    return vplbm
+
+
+def _run(sim, n, chunk=20000):
+    out = []
+    done = 0
+    while done < n:
+        k = min(chunk, n - done)
+        sim.step(k)
+        out.append(sim.forces())
+        done += k
+    return np.concatenate(out)
+
+
+def test_paper_imposed_oscillation_mean_drag(gpu):
+    wl = W.paper_imposed_oscillation(storage="fp64")
+    U0, D, T = wl["U0"], wl["D"], wl["period"]
+    s = 0.5 * U0 ** 2 * D
+    _flush("paper imposed oscillation 1230x410 fp64: fixed-cylinder run")
+    g = gpu.Sim(wl["spec"], wl["fixed"])
+    g.set_graph_steps(64)
+    pre = _run(g, 100000)
+    cl = pre["fmem"][50000:, 1] / s
+    zc = np.where(np.diff(np.sign(cl - cl.mean())) > 0)[0]
+    st = D / (np.diff(zc).mean() * U0)
+    _flush("fixed cylinder: CD %.4f, St %.4f" % (pre["fmem"][-10000:, 0].mean() / s, st))
+    assert 0.15 <= st <= 0.19  # periodic shedding at Re = 100 before the motion starts
+    g.set_body(wl["body"])
+    k = int(64.0 * D / U0 // T)  # whole periods up to t* = 64
+    n = int(round(k * T))
+    r = _run(g, n)
+    g.close()
+    cd_mem = r["fmem"][:, 0].mean() / s
+    cd_h = r["fh"][:, 0].mean() / s
+    _flush("moving, %d periods: mean CD %.4f (momentum exchange), %.4f (penalization); "
+           "paper 1.653" % (k, cd_mem, cd_h))
+    y = r["q"][:, 1]
+    assert abs(y.max() - wl["fixed"]["y"]) < 1e-9 and abs(y.min() - (wl["fixed"]["y"] - 2 * wl["body"]["imp_amp"])) < 1e-3
+    assert abs(cd_mem / 1.653 - 1.0) <= 0.02
+    assert abs(cd_h / cd_mem - 1.0) <= 0.01
+
+
+def test_paper_centred_settling_velocities(gpu):
+    wls = [W.paper_sedimentation_centered(r, storage="fp64") for r in W.PAPER_DENSITY_RATIOS]
+    _flush("paper centred settling: 6 runs of 1200x120 in one batch, 30000 steps")
+    b = gpu.Batch([(w["spec"], w["body"]) for w in wls], storage="fp64", graph_steps=64)
+    recs = [[] for _ in wls]
+    for _ in range(6):
+        b.step(5000)
+        for i, sm in enumerate(b.sims):
+            recs[i].append(sm.forces())
+    b.close()
+    ratio = {}
+    for w, rl in zip(wls, recs):
+        r = np.concatenate(rl)
+        rr = W.PAPER_DENSITY_RATIOS[wls.index(w)]
+        ratio[rr] = r["v"][-5000:, 0].mean() / w["vs"]
+        _flush("rho_r %.2f: terminal / closed form %.4f" % (rr, ratio[rr]))
+        # the centred disc stays on the mirror line and does not turn
+        assert np.abs(r["q"][:, 1] - w["body"]["y"]).max() <= 1e-12
+        assert np.abs(r["v"][:, 2]).max() <= 1e-12
+    for rr in (0.98, 0.99, 1.01, 1.02):
+        assert 0.95 <= ratio[rr] <= 1.02, (rr, ratio[rr])
+    for rr in (0.95, 1.05):
+        assert 0.85 <= ratio[rr] < min(ratio[0.98], ratio[1.02])
+    # Stokes regime: a lighter and a heavier disc of the same |1 - rho_r| mirror each other
+    for a, c in ((0.99, 1.01), (0.98, 1.02), (0.95, 1.05)):
+        assert abs(ratio[a] / ratio[c] - 1.0) <= 2e-3

@@ -46,14 +46,14 @@ def force_err(ra, rb, radius=None):
     R * max|F|, which is added to their scale."""
     out = {}
     R = radius if radius is not None else 0.0
-    fscale = max(np.abs(rb["fvp"]).max(), np.abs(rb["fh"]).max())
+    fscale = max(np.abs(rb["fvp"]).max(), np.abs(rb["fh"]).max(), np.abs(rb["fmem"]).max())
     pscale = np.abs(rb["pin"][:, :2]).max() if len(rb) else 0.0
-    for key in ("fvp", "fh"):
+    for key in ("fvp", "fh", "fmem"):
         out[key] = rel(ra[key], rb[key])
     out["pin"] = max(np.abs(ra["pin"][:, :2] - rb["pin"][:, :2]).max() / max(pscale, 1e-300),
                      np.abs(ra["pin"][:, 2] - rb["pin"][:, 2]).max()
                      / max(np.abs(rb["pin"][:, 2]).max() + R * pscale, 1e-300))
-    for key in ("tvp", "th"):
+    for key in ("tvp", "th", "tmem"):
         out[key] = np.abs(ra[key] - rb[key]).max() / max(np.abs(rb[key]).max() + R * fscale,
                                                           1e-300)
     out["q"] = np.abs(ra["q"] - rb["q"]).max()
@@ -75,13 +75,19 @@ UWALL = [[0.04, 0.01], [0.0, 0.0], [0.0, 0.0], [0.03, -0.005]]
 def body_of(kind, nx, ny, smooth):
     D = min(nx, ny) * 0.45
     b = W.fixed_disc(D, nx * 0.42 + 0.17, ny * 0.5 - 0.23, smooth_delta=1.0 if smooth else 0.0)
+    b["force_model"] = "vp+mem"  # record the momentum-exchange load alongside
     if kind == "fixed":
         b.update(vx=0.002, omega=0.001)
     elif kind == "imposed":
-        b.update(mode="imposed_sin", imp_amp=0.8, imp_freq=0.05, imp_y0=ny * 0.5 - 0.23)
+        b.update(mode="imposed_sin", imp_amp=0.8, imp_freq=0.05, imp_y0=ny * 0.5 - 0.23,
+                 imp_phase=0.7)
     elif kind == "free":
         b.update(mode="free", free_mask=7, mass=400.0, inertia=3000.0, k=(0.01, 0.02, 0.0),
                  c=(0.001, 0.0, 0.0), q0=(b["x"], b["y"], 0.0), f_ext=(1e-4, -2e-4, 0.0))
+    elif kind == "free_mem":  # driven by the momentum-exchange load
+        b.update(mode="free", free_mask=7, mass=400.0, inertia=3000.0, k=(0.01, 0.02, 0.0),
+                 c=(0.001, 0.0, 0.0), q0=(b["x"], b["y"], 0.0), f_ext=(1e-4, -2e-4, 0.0),
+                 force_model="mem")
     elif kind == "const_vel":
         b.update(mode="const_vel", vx=0.03, vy=-0.02, omega=0.004)
     return b
@@ -110,7 +116,12 @@ def run_pair(gpu, spec, body, steps, seed, check_every=1, tol=1e-12, init_random
             assert len(rg) == 0  # steps without a body have no record
             continue
         fe = force_err(rg, ro, body["radius"])
-        for key in ("fvp", "tvp", "pin", "fh", "th"):
+        keys = ["fvp", "tvp", "pin", "fh", "th"]
+        if body.get("force_model", "vp") in ("mem", "vp+mem"):
+            keys += ["fmem", "tmem"]
+        else:
+            assert not rg["fmem"].any() and not rg["tmem"].any()
+        for key in keys:
             if np.abs(ro[key]).max() > 1e-14:
                 assert fe[key] <= tol * 10, (s, key, fe)
         assert fe["q"] <= 1e-12 * max(nx, ny) and fe["v"] <= 1e-12, (s, fe)
@@ -119,7 +130,7 @@ def run_pair(gpu, spec, body, steps, seed, check_every=1, tol=1e-12, init_random
 
 
 @pytest.mark.parametrize("bcname", list(BCS))
-@pytest.mark.parametrize("bodykind", ["none", "fixed", "imposed", "free", "const_vel"])
+@pytest.mark.parametrize("bodykind", ["none", "fixed", "imposed", "free", "free_mem", "const_vel"])
 @pytest.mark.parametrize("smooth", [False, True])
 def test_tiny_grids_step_by_step_fp64(gpu, bcname, bodykind, smooth):
     if bodykind == "none" and smooth:
@@ -227,6 +238,7 @@ def test_imposed_oscillation_full_run_fp64(gpu):
     record and the final fields against the oracle."""
     from oracle import oracle as orc
     wl = W.imposed_oscillation(storage="fp64")
+    wl["body"]["force_model"] = "vp+mem"
     _flush("imposed oscillation fp64 2000 steps")
     o = orc.OracleSim(wl["spec"], wl["body"])
     g = gpu.Sim(wl["spec"], wl["body"])
@@ -238,7 +250,7 @@ def test_imposed_oscillation_full_run_fp64(gpu):
     fe = force_err(rg, ro, wl["body"]["radius"])
     _flush("fp64 2000 steps: %s" % fe)
     assert fe["fvp"] <= 1e-12 and fe["tvp"] <= 1e-12 and fe["pin"] <= 1e-12, fe
-    assert fe["fh"] <= 1e-11, fe
+    assert fe["fh"] <= 1e-11 and fe["fmem"] <= 1e-11 and fe["tmem"] <= 1e-11, fe
     assert fe["q"] <= 1e-12, fe
     rho_o, ux_o, uy_o = o.fields()
     rho_g, ux_g, uy_g = g.fields()
@@ -423,4 +435,36 @@ def test_records_exist_only_for_steps_with_a_body(gpu):
     g.step(2)
     r = g.forces()
     assert list(r["step"]) == [9, 10] and np.isfinite(r["fvp"]).all()
+    g.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_momentum_exchange_reduced_storage_one_step(gpu, storage):
+    """Momentum-exchange load of one step from a common stored state, FP32 arithmetic:
+    every link term (e - u_G) f carries at most the one-step storage error of f
+    (the populations test's bound, relative to max f) times |e - u_G| <= 1.5, so the
+    force error is bounded by that times the number of link terms."""
+    from oracle import oracle as orc
+    nx, ny = 40, 36
+    spec = spec_of(nx, ny, BCS["periodic"], storage=storage)
+    body = W.fixed_disc(17.3, 19.4, 17.8)
+    body.update(vx=0.004, vy=-0.003, omega=0.0015, force_model="vp+mem")
+    tol = {"fp32": 2e-7, "fp16": 5e-5, "bf16": 5e-4}[storage]
+    g = gpu.Sim(spec, body)
+    g.set_populations(W.random_populations(nx, ny, seed=91, amp=0.05))
+    o = orc.OracleSim(spec, body)
+    o.set_populations(g.get_populations())
+    cx, cy, _, _, _, _ = orc.lattice()
+    R2 = body["radius"] ** 2
+    solid = lambda i, j: (i - body["x"]) ** 2 + (j - body["y"]) ** 2 <= R2
+    terms = sum(1 for j in range(ny) for i in range(nx) for a in range(1, 9)
+                if solid(i, j) != solid(i + cx[a], j + cy[a]))
+    g.step(1)
+    ro, rg = o.step(1), g.forces()
+    fmax = o.get_populations().max()
+    bound = terms * 1.5 * tol * fmax
+    _flush("%s: %d link terms, fmem err %.3e (bound %.3e)" % (
+        storage, terms, np.abs(rg["fmem"] - ro["fmem"]).max(), bound))
+    assert np.abs(rg["fmem"] - ro["fmem"]).max() <= bound
+    assert abs(rg["tmem"][0] - ro["tmem"][0]) <= bound * (body["radius"] + 1.0)
     g.close()
