@@ -60,6 +60,14 @@ def parse():
     return ap.parse_args()
 
 
+def split_warmup(warmup, graph_steps):
+    """Untimed steps before and after the launch configuration is chosen: the
+    autotuner times its candidates from the developed flow, and the steps after it
+    capture the graphs of the timed region.  Together they are the requested warm-up."""
+    post = min(warmup // 2, max(2 * graph_steps, 128))
+    return warmup - post, post
+
+
 def cpu_baseline(wl, target_seconds):
     """FP64 CPU oracle on the same grid for a bounded number of steps."""
     from oracle import oracle as orc
@@ -186,13 +194,16 @@ def run_batch(args):
         batch = vplbm.Batch(members, storage=args.storage, rows=rows, store=args.store,
                             history_cap=4096, stream=stream.cuda_stream)
         tuned = None
+        w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
+        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+        batch.step(w_pre)
+        batch.sync()
         if not args.no_autotune and args.rows == 0 and args.store == "auto":
             print("autotune", file=sys.stderr, flush=True)
             tuned = batch.autotune(trial_steps=20)
         if args.graph_steps:
             batch.set_graph_steps(args.graph_steps)
-        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-        batch.step(args.warmup)
+        batch.step(w_post)
         batch.sync()
         torch.cuda.synchronize()
         print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
@@ -352,14 +363,17 @@ def main():
     with torch.cuda.stream(stream):
         sim = vplbm.Sim(spec, body, torch_memory=True, history_cap=1 << 17)
         tuned = None
+        w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
+        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+        sim.step(w_pre)
+        sim.sync()
         if not args.no_autotune and args.rows == 0 and args.store == "auto":
             print("autotune", file=sys.stderr, flush=True)
             tuned = sim.autotune(trial_steps=50)
         rows, nt = (tuned[0], tuned[1]) if tuned else (None, None)
         if args.graph_steps:
             sim.set_graph_steps(args.graph_steps)
-        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-        sim.step(args.warmup)
+        sim.step(w_post)
         sim.sync()
         torch.cuda.synchronize()
         # timed region: K full steps on the simulation's stream, bracketed by events

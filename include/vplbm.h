@@ -73,6 +73,12 @@ enum { LBM_REF_INITIAL = 0, LBM_REF_REST = 1 };
  * them past the caches; AUTO picks NONTEMPORAL above 1 GiB of buffers. */
 enum { LBM_STORE_AUTO = 0, LBM_STORE_PLAIN = 1, LBM_STORE_NONTEMPORAL = 2 };
 
+/* Collision operator.  MRT relaxes the moments of Eq. (9) at the rates of lbm_rates
+ * (Eqs. (8), (16)); BGK (Sec. 2.2, Eqs. (11)-(12) with Guo's source) relaxes every
+ * population at 1/tau = s_nu, which is MRT with all rates equal to s_nu: with it,
+ * s_e, s_eps and s_q are ignored. */
+enum { LBM_COLLIDE_MRT = 0, LBM_COLLIDE_BGK = 1 };
+
 /* Boundary rule of one domain side (Sec. 3.1 for the channel set-up).
  *   PERIODIC  wrap around (both opposite sides must be periodic);
  *   WALL      no-slip half-way bounce-back;
@@ -128,6 +134,7 @@ typedef struct {
     int store_mode;        /* LBM_STORE_AUTO (default), _PLAIN or _NONTEMPORAL */
     void* hip_stream;      /* hipStream_t to run on; NULL: the library creates one */
     void* pop_buffers[2];  /* optional caller-owned device buffers of lbm_pop_bytes() each */
+    int collision;         /* LBM_COLLIDE_MRT (default) or LBM_COLLIDE_BGK */
 } lbm_opts;
 
 typedef struct {
@@ -232,8 +239,10 @@ int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms
 
 /* Chooses the launch configuration of the step kernel (rows per tile 1/2/4, plain or
  * nontemporal stores) by timing trial_steps steps of each candidate on a scratch
- * simulation of the same grid and storage, and applies it to sim (whose state is not
- * touched).  cache_path (may be NULL) names a JSON-lines file: a configuration found
+ * simulation of the same grid, storage and body, started from a copy of sim's current
+ * populations and outflow memory (call it once the flow has developed: the uniform
+ * start state is exactly zero in offsets and moves faster than a developed flow), and
+ * applies it to sim (whose state is not touched).  cache_path (may be NULL) names a JSON-lines file: a configuration found
  * there for this device, storage and grid is applied without timing, and a newly
  * timed one is appended.  Outputs (each may be NULL): the chosen rows, nt flag, and
  * the measured time per step in microseconds (-1 when taken from the cache). */

@@ -7,7 +7,9 @@ A simulation is described by two plain dicts shared with the GPU binding (their
 keys only; no code is shared):
 
 * ``spec``: ``nx, ny, rates=(s_e, s_eps, s_q, s_nu), eta, bc=(west, east, south,
-  north), u_wall (4x2), u_conv, g_fluid (2), rho0, u0 (2)``;
+  north), u_wall (4x2), u_conv, g_fluid (2), rho0, u0 (2)``, and ``collision``
+  (``"mrt"``, or ``"bgk"``: every rate 1/tau = s_nu, which the BGK pin equates with
+  the single-relaxation-time collision and Guo's source);
 * ``body``: ``radius, x, y, theta, vx, vy, omega, mode, free_mask, mass, inertia,
   k, c, q0, f_ext (3 each), imp_amp, imp_freq, imp_y0, imp_phase, smooth_delta,
   internal_mass_correction, force_model`` (``"vp"``, ``"mem"`` or ``"vp+mem"``: the load
@@ -150,7 +152,10 @@ def relaxation_vector(rates, conserved=None):
 def make_params(spec, body=None, conserved=None) -> Params:
     p = Params()
     p.nx, p.ny = int(spec["nx"]), int(spec["ny"])
-    for k, v in enumerate(relaxation_vector(spec["rates"], conserved)):
+    rates = spec["rates"]
+    if spec.get("collision", "mrt") == "bgk":  # single relaxation time 1/tau = s_nu
+        rates = (rates[3],) * 4
+    for k, v in enumerate(relaxation_vector(rates, conserved)):
         p.s[k] = float(v)
     p.eta = float(spec["eta"])
     bc = spec.get("bc", ("periodic",) * 4)

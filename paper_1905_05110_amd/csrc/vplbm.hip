@@ -127,6 +127,8 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
     if (o.rows_per_tile != 0 && o.rows_per_tile != 1 && o.rows_per_tile != 2 &&
         o.rows_per_tile != 4)
         return m = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
+    if (o.collision != LBM_COLLIDE_MRT && o.collision != LBM_COLLIDE_BGK)
+        return m = "collision must be LBM_COLLIDE_MRT or LBM_COLLIDE_BGK", LBM_ERR_ARG;
     if (o.store_mode < LBM_STORE_AUTO || o.store_mode > LBM_STORE_NONTEMPORAL)
         return m = "unknown store mode", LBM_ERR_ARG;
     if (o.offset_ref != LBM_REF_INITIAL && o.offset_ref != LBM_REF_REST)
@@ -163,6 +165,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     std::string msg;
     int rc = check_opts(nx, ny, rates, eta, o, msg);
     if (rc) return g_create_error = msg, rc;
+    if (o.collision == LBM_COLLIDE_BGK) rates.s_e = rates.s_eps = rates.s_q = rates.s_nu;
 
     lbm_sim* s = new lbm_sim();
     s->nx = nx;
@@ -673,6 +676,11 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
     int rows = 0, nt = 0;
     double best = -1.0;
     if (!(cache_path && tune_lookup(cache_path, key, rows, nt))) {
+        // candidates are timed from this simulation's current state, not from the uniform
+        // start (whose exactly-zero offsets the memory system moves faster)
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        const int cur = (int)(s->host_step & 1);
+        const size_t outlet_bytes = 3 * (size_t)s->ny * (s->storage == LBM_FP64 ? 8 : 4);
         const int cand_rows[3] = {1, 2, 4};
         for (int ci = 0; ci < 6; ++ci) {
             lbm_opts o = s->opts;
@@ -690,7 +698,11 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
             }
             hipEvent_t e0, e1;
             float ms = 0.f;
-            bool ok = lbm_step(t, 3) == LBM_OK && hipEventCreate(&e0) == hipSuccess &&
+            bool ok = hipMemcpyAsync(t->pop[0], s->pop[cur], s->pop_bytes, hipMemcpyDeviceToDevice,
+                                     t->stream) == hipSuccess &&
+                      hipMemcpyAsync(t->outlet, s->outlet, outlet_bytes, hipMemcpyDeviceToDevice,
+                                     t->stream) == hipSuccess &&
+                      lbm_step(t, 3) == LBM_OK && hipEventCreate(&e0) == hipSuccess &&
                       hipEventCreate(&e1) == hipSuccess &&
                       hipEventRecord(e0, t->stream) == hipSuccess &&
                       lbm_step(t, trial_steps) == LBM_OK &&
@@ -1133,9 +1145,19 @@ static int batch_time(lbm_batch* b, int rows, bool nt, int order, int trial_step
     lbm_batch* t = nullptr;
     int rc = lbm_batch_create(b->n, ds.data(), &bo, &t);
     if (rc) return bfail(b, rc, std::string("autotune: ") + lbm_batch_last_error(nullptr));
+    // the candidates run from the members' current states (see lbm_autotune)
+    bool ok = hipStreamSynchronize(b->stream) == hipSuccess;
+    for (int i = 0; ok && i < b->n; ++i) {
+        const lbm_sim* m = b->sims[i];
+        const size_t outlet_bytes = 3 * (size_t)m->ny * (m->storage == LBM_FP64 ? 8 : 4);
+        ok = hipMemcpyAsync(t->sims[i]->pop[0], m->pop[m->host_step & 1], m->pop_bytes,
+                            hipMemcpyDeviceToDevice, t->stream) == hipSuccess &&
+             hipMemcpyAsync(t->sims[i]->outlet, m->outlet, outlet_bytes, hipMemcpyDeviceToDevice,
+                            t->stream) == hipSuccess;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms = 0.f;
-    bool ok = lbm_batch_step(t, 3) == LBM_OK && hipEventCreate(&e0) == hipSuccess &&
+    ok = ok && lbm_batch_step(t, 3) == LBM_OK && hipEventCreate(&e0) == hipSuccess &&
               hipEventCreate(&e1) == hipSuccess && hipEventRecord(e0, t->stream) == hipSuccess &&
               lbm_batch_step(t, trial_steps) == LBM_OK &&
               hipEventRecord(e1, t->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&

@@ -997,12 +997,16 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
         if (lane == 0) red[wave][k] = s;
     }
     // the momentum-exchange pass runs once the other sums have left the registers
-    double m[3];
-    mem_pass<S, ROWS>(d, tx, ty, p, pose, m);
+    if (B.mem) {  // uniform
+        double m[3];
+        mem_pass<S, ROWS>(d, tx, ty, p, pose, m);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double s = wave_sum(m[k]);
-        if (lane == 0) red[wave][NRED - 3 + k] = s;
+        for (int k = 0; k < 3; ++k) {
+            const double s = wave_sum(m[k]);
+            if (lane == 0) red[wave][NRED - 3 + k] = s;
+        }
+    } else if (lane < 3) {
+        red[wave][NRED - 3 + lane] = 0.0;
     }
     __syncthreads();
     if (threadIdx.x < NRED) {

@@ -55,7 +55,7 @@ class Opts(C.Structure):
                 ("storage", C.c_int), ("fp16_scale_log2", C.c_int), ("history_cap", C.c_int),
                 ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
                 ("hip_stream", C.c_void_p),
-                ("pop_buffers", C.c_void_p * 2)]
+                ("pop_buffers", C.c_void_p * 2), ("collision", C.c_int)]
 
 
 class Body(C.Structure):
@@ -187,6 +187,7 @@ def make_opts(spec, stream=None, buffers=None, history_cap=65536):
     o.offset_ref = {"initial": 0, "rest": 1}[spec.get("offset_ref", "initial")]
     o.rows_per_tile = int(spec.get("rows_per_tile", 0))
     o.store_mode = {"auto": 0, "plain": 1, "nontemporal": 2}[spec.get("store_mode", "auto")]
+    o.collision = {"mrt": 0, "bgk": 1}[spec.get("collision", "mrt")]
     o.hip_stream = stream
     if buffers is not None:
         o.pop_buffers[0], o.pop_buffers[1] = buffers

@@ -468,3 +468,15 @@ def test_momentum_exchange_reduced_storage_one_step(gpu, storage):
     assert np.abs(rg["fmem"] - ro["fmem"]).max() <= bound
     assert abs(rg["tmem"][0] - ro["tmem"][0]) <= bound * (body["radius"] + 1.0)
     g.close()
+
+
+@pytest.mark.parametrize("bcname", ["channel", "periodic", "wallbox", "mixed"])
+@pytest.mark.parametrize("bodykind", ["none", "fixed", "free"])
+def test_bgk_collision_step_by_step_fp64(gpu, bcname, bodykind):
+    """The BGK operator (Sec. 2.2, Eqs. (11)-(12) with Guo's source): relaxation of every
+    population at 1/tau = s_nu, the other rates given but ignored."""
+    nx, ny = 13, 11
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04)
+    spec.update(collision="bgk", rates=(1.1, 1.25, 1.8, 1.0 / 0.62))
+    body = None if bodykind == "none" else body_of(bodykind, nx, ny, False)
+    run_pair(gpu, spec, body, steps=6, seed=4321)

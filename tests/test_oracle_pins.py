@@ -131,6 +131,10 @@ def test_mrt_with_equal_rates_is_bgk_plus_guo(orc):
             F = orc.guo(u[0], u[1], G[0], G[1])
             bgk = P - (P - feq) / tau + (1 - 1 / (2 * tau)) * F
             assert np.abs(out - bgk).max() <= 1e-15  # ulp level; forcing terms are ~1e-5
+            # the BGK operator selected by name ignores the other rates
+            sb = dict(spec, rates=(1.1, 1.25, 1.8, s), collision="bgk")
+            out_b = orc.node(sb, P, chi, us)[0]
+            assert np.abs(out_b - bgk).max() <= 1e-15
 
 
 def test_conserved_moment_rates_do_not_matter(orc):
