@@ -11,6 +11,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <cstddef>
 #include <stdint.h>
 
 namespace vplbm {
@@ -222,6 +224,10 @@ struct Codec<bf16s> {
     }
 };
 
+// Fourth word of a raw buffer resource descriptor on this architecture (32-bit data
+// format; no swizzle, no index stride).
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
+
 // Global-memory load and store of a T through an address-space-1 pointer.
 template <class T>
 __device__ __forceinline__ T gld(const T* p) {
@@ -232,6 +238,14 @@ __device__ __forceinline__ void gst(T* p, T v) {
     *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// Raise bits of the simulation's status flag with a global (not flat) atomic: a flat
+// memory operation is also counted by the scalar-load counter, so later waits for
+// scalar loads would wait for it too.
+__device__ __forceinline__ void raise_flag(int* flag, int bits) {
+    __hip_atomic_fetch_or((__attribute__((address_space(1))) int*)flag, bits, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class S>
 __device__ __forceinline__ unsigned node_off(const SimDesc& d, int i, int j) {
     return ((unsigned)j * (unsigned)d.pitch + (unsigned)i) * (unsigned)sizeof(S);
@@ -240,6 +254,55 @@ __device__ __forceinline__ unsigned node_off(const SimDesc& d, int i, int j) {
 template <class S>
 __device__ __forceinline__ const char* plane(const SimDesc& d, const void* buf, int a) {
     return reinterpret_cast<const char*>(buf) + (long long)a * d.ps * (long long)sizeof(S);
+}
+
+// The scalars of a step that a tile's fast path uses (buffers, layout, the collision
+// constants), read once at the start of the tile.  Read there, ahead of every other
+// memory operation of the tile, they come in with one round of scalar loads and stay in
+// scalar registers; read from the descriptor where they are used, after a load or an
+// atomic the compiler has to order them behind, each came back as a vector load with
+// a full memory round trip of its own.
+template <class T>
+struct TileScalars {
+    const char* fin;   // populations read by the step
+    char* fout;        // populations written
+    long long psb;     // plane stride in bytes
+    unsigned rowb;     // row pitch in bytes
+    int pitch, nx, ny;
+    float scale, inv_scale;
+    int* flag;
+    T s_e, s_eps, s_q, s_nu, h_e, h_eps, h_q, h_nu, inv_eta, gx, gy, u0x, u0y;
+};
+
+template <class S>
+__device__ __forceinline__ TileScalars<typename Codec<S>::T> tile_scalars(const SimDesc& d, int p) {
+    using T = typename Codec<S>::T;
+    const Consts<T>& c = consts_of<T>(d);
+    TileScalars<T> t;
+    t.fin = reinterpret_cast<const char*>(d.pop[p]);
+    t.fout = reinterpret_cast<char*>(d.pop[p ^ 1]);
+    t.psb = d.ps * (long long)sizeof(S);
+    t.pitch = d.pitch;
+    t.rowb = (unsigned)d.pitch * (unsigned)sizeof(S);
+    t.nx = d.nx;
+    t.ny = d.ny;
+    t.scale = d.scale;
+    t.inv_scale = d.inv_scale;
+    t.flag = d.flag;
+    t.s_e = c.s_e;
+    t.s_eps = c.s_eps;
+    t.s_q = c.s_q;
+    t.s_nu = c.s_nu;
+    t.h_e = c.h_e;
+    t.h_eps = c.h_eps;
+    t.h_q = c.h_q;
+    t.h_nu = c.h_nu;
+    t.inv_eta = c.inv_eta;
+    t.gx = c.gx;
+    t.gy = c.gy;
+    t.u0x = c.u0x;
+    t.u0y = c.u0y;
+    return t;
 }
 
 // ---- streaming with boundary rules (Eq. (18) applied as a pull) -----------------------
@@ -484,8 +547,8 @@ __device__ __forceinline__ float recip<float>(float x) {
 // ds = u_s - u_ref:  r = (jg - drho u_ref + rho g/2 - rho ds) / (rho (1 + lam/2)),
 // u - u_ref = ds + r.  Where chi = 0 the result does not depend on u_s, and ds = 0
 // is passed so that no term cancels against u_ref.
-template <class T, bool VP = true>
-__device__ __forceinline__ void macros(const Consts<T>& c, const T g[NQ], T chi, T dsx, T dsy,
+template <class T, bool VP = true, class C>
+__device__ __forceinline__ void macros(const C& c, const T g[NQ], T chi, T dsx, T dsy,
                                        NodeOut<T>& o) {
     const T s1234 = (g[1] + g[2]) + (g[3] + g[4]);
     const T s5678 = (g[5] + g[6]) + (g[7] + g[8]);
@@ -524,8 +587,8 @@ __device__ __forceinline__ void macros(const Consts<T>& c, const T g[NQ], T chi,
 // F the Guo forcing vector of Eq. (12) without its (1 - 1/2tau) factor, whose moments
 // are (0, 6 u.G, -6 u.G, Gx, -Gx, Gy, -Gy, 2(ux Gx - uy Gy), ux Gy + uy Gx).
 // The conserved moments come out as rho, j + G whatever their rates.
-template <class T, bool VP = true>
-__device__ __forceinline__ void collide(const Consts<T>& c, const T g[NQ], T chi, T dsx, T dsy,
+template <class T, bool VP = true, class C>
+__device__ __forceinline__ void collide(const C& c, const T g[NQ], T chi, T dsx, T dsy,
                                         T out[NQ], NodeOut<T>& o) {
     macros<T, VP>(c, g, chi, dsx, dsy, o);
     const T drho = o.drho, Gx = o.Gx, Gy = o.Gy;
@@ -652,35 +715,36 @@ __device__ __forceinline__ double wave_sum(double v) {
 // chi and u_s and accumulate force, torque and internal momentum in FP64.
 // First row of a tile: the pulled offsets of node (i, j0), interior or edge.
 template <class S>
-__device__ __forceinline__ void pull_first(const SimDesc& d, int p, int tx, int ty, int rows,
-                                           typename Codec<S>::T g[NQ]) {
+__device__ __forceinline__ void pull_first(const SimDesc& d,
+                                           const TileScalars<typename Codec<S>::T>& ts, int tx,
+                                           int ty, int rows, typename Codec<S>::T g[NQ]) {
     const int i = tx * TILE_X + (int)threadIdx.x;
     const int j0 = ty * rows;
     // a wave with any edge node takes the boundary-rule pull for all its lanes (it
     // handles interior nodes too): one path and one round of loads per wave
-    const bool inner = i >= 1 && i <= d.nx - 2 && j0 >= 1 && j0 <= d.ny - 2;
+    const bool inner = i >= 1 && i <= ts.nx - 2 && j0 >= 1 && j0 <= ts.ny - 2;
     if (__all(inner)) {
         const char* P[NQ];
 #pragma unroll
-        for (int a = 0; a < NQ; ++a) P[a] = plane<S>(d, d.pop[p], a);
-        pull_interior<S>(P, node_off<S>(d, i, j0), (unsigned)d.pitch * (unsigned)sizeof(S),
-                         d.inv_scale, g);
-    } else if (i < d.nx && j0 < d.ny) {
-        pull_edge<S>(d, d.pop[p], d.outlet, i, j0, g, true);
+        for (int a = 0; a < NQ; ++a) P[a] = ts.fin + (long long)a * ts.psb;
+        pull_interior<S>(P, ((unsigned)j0 * (unsigned)ts.pitch + (unsigned)i) * (unsigned)sizeof(S),
+                         ts.rowb, ts.inv_scale, g);
+    } else if (i < ts.nx && j0 < ts.ny) {
+        pull_edge<S>(d, ts.fin, d.outlet, i, j0, g, true);
     }
 }
 
 template <class S, int ROWS, bool NT, bool PART>
-__device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int p,
-                                          double acc[NRED], const double* pose,
+__device__ __forceinline__ void step_rows(const SimDesc& d,
+                                          const TileScalars<typename Codec<S>::T>& c, int tx,
+                                          int ty, double acc[NRED], const double* pose,
                                           typename Codec<S>::T g[NQ]) {
     using T = typename Codec<S>::T;
-    const Consts<T>& c = consts_of<T>(d);
-    const void* fin = d.pop[p];
-    char* fout = reinterpret_cast<char*>(d.pop[p ^ 1]);
+    const char* fin = c.fin;
+    char* fout = c.fout;
     const int i = tx * TILE_X + (int)threadIdx.x;
     const int j0 = ty * ROWS;
-    const int nx = d.nx, ny = d.ny;
+    const int nx = c.nx, ny = c.ny;
     const bool col_ok = i < nx;
     const bool col_inner = i >= 1 && i <= nx - 2;
 
@@ -688,11 +752,11 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
     char* Q[NQ];
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
-        P[a] = plane<S>(d, fin, a);
-        Q[a] = fout + (long long)a * d.ps * (long long)sizeof(S);
+        P[a] = fin + (long long)a * c.psb;
+        Q[a] = fout + (long long)a * c.psb;
     }
-    const unsigned rowb = (unsigned)d.pitch * (unsigned)sizeof(S);
-    const float is = d.inv_scale;
+    const unsigned rowb = c.rowb;
+    const float is = c.inv_scale;
 
     T gn[NQ];
 #pragma unroll
@@ -701,7 +765,8 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
         if (j >= ny) break;  // uniform over the workgroup
         if (r + 1 < ROWS && j + 1 < ny) {  // uniform
             if (__all(col_inner && j + 1 <= ny - 2))
-                pull_interior<S>(P, node_off<S>(d, i, j + 1), rowb, is, gn);
+                pull_interior<S>(P, ((unsigned)(j + 1) * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S),
+                                 rowb, is, gn);
             else if (col_ok)
                 pull_edge<S>(d, fin, d.outlet, i, j + 1, gn, true);
         }
@@ -743,11 +808,11 @@ __device__ __forceinline__ void step_rows(const SimDesc& d, int tx, int ty, int 
             } else {
                 collide<T, false>(c, g, T(0), T(0), T(0), out, o);
             }
-            const unsigned off = node_off<S>(d, i, j);
+            const unsigned off = ((unsigned)j * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S);
 #pragma unroll
-            for (int a = 0; a < NQ; ++a) Codec<S>::template store<NT>(Q[a], off, out[a], d.scale);
+            for (int a = 0; a < NQ; ++a) Codec<S>::template store<NT>(Q[a], off, out[a], c.scale);
             if (!(o.rho > T(0)) || !__builtin_isfinite(o.ux) || !__builtin_isfinite(o.uy))
-                atomicOr(d.flag, 1);
+                raise_flag(c.flag, 1);
         }
         if (r + 1 < ROWS) {
 #pragma unroll
@@ -951,17 +1016,28 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     __shared__ double pose[6];
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
-    // the participation box (both parities read, then selected: no dependent load), then
-    // the first row's populations, which stay in flight while the box is tested
-    const int fresh = B.st[p].fresh;
+    // the first row's populations, then the participation box (both parities read, then
+    // selected: no dependent load)
+    // the step's scalars first, then the first row's populations
+    const TileScalars<T> ts = tile_scalars<S>(d, p);
+    T g[NQ];
+    pull_first<S>(d, ts, tx, ty, ROWS, g);
+    // Then the participation box, as vector-memory (buffer) loads issued behind the
+    // population loads: their wait is counted in order with those, which the collision
+    // waits for anyway.  (Scalar or flat loads ahead of the pull would be waited for,
+    // with every other scalar load, before the population loads are issued.)  The
+    // descriptor covers the two state slots exactly; reads beyond it would return 0.
+    const __amdgpu_buffer_rsrc_t bst = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)&B.st[0], (short)0, (int)sizeof(B.st), BUFFER_RSRC_WORD3);
+    const int sp = p * (int)sizeof(BodyState), sq = (p ^ 1) * (int)sizeof(BodyState);
+    constexpr int o_fresh = (int)offsetof(BodyState, fresh), o_box = (int)offsetof(BodyState, boxM);
+    const int fresh = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_fresh, 0, 0);
     int box_p[4], box_q[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        box_p[k] = B.st[p].boxM[k];
-        box_q[k] = B.st[p ^ 1].boxM[k];
+        box_p[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_box + 4 * k, 0, 0);
+        box_q[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sq + o_box + 4 * k, 0, 0);
     }
-    T g[NQ];
-    pull_first<S>(d, p, tx, ty, ROWS, g);
     int pb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) pb[k] = fresh ? box_p[k] : box_q[k];
@@ -969,7 +1045,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
     double acc[NRED];
     if (!part) {
-        step_rows<S, ROWS, NT, false>(d, tx, ty, p, acc, nullptr, g);
+        step_rows<S, ROWS, NT, false>(d, ts, tx, ty, acc, nullptr, g);
         return;  // uniform over the workgroup
     }
     const bool writer = tx == bx0 && ty == by0;
@@ -988,7 +1064,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
-    step_rows<S, ROWS, NT, true>(d, tx, ty, p, acc, pose, g);
+    step_rows<S, ROWS, NT, true>(d, ts, tx, ty, acc, pose, g);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -1022,7 +1098,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
             const BodyState& prev = B.st[p ^ 1];
             int exact[4];
             body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], exact, 1.0);
-            if (!box_inside(exact, pb)) atomicOr(d.flag, 2);  // moved >= 2 nodes in a step
+            if (!box_inside(exact, pb)) raise_flag(d.flag, 2);  // moved >= 2 nodes in a step
             write_record(d, prev, bs);
             store_state(B.st[p], prev, bs, 0);
         }
@@ -1043,7 +1119,7 @@ __device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
         const BodyState& prev = B.st[p ^ 1];
         int exact[4];
         body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], exact, 1.0);
-        if (!box_inside(exact, prev.boxM)) atomicOr(d.flag, 2);
+        if (!box_inside(exact, prev.boxM)) raise_flag(d.flag, 2);
         write_record(d, prev, bs);
         store_state(B.st[p], prev, bs, 1);
     }
