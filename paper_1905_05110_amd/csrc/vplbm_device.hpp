@@ -380,19 +380,30 @@ __device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_
                           typename Codec<S>::T g[NQ], bool update_outlet) {
     using T = typename Codec<S>::T;
     const Consts<T>& c = consts_of<T>(d);
+    // uniform parameters, read together ahead of the lane-dependent logic
     const int nx = d.nx, ny = d.ny;
-    // boundary kinds as uniform values: no lane-dependent indexing into memory
     const int kW = d.bc[0], kE = d.bc[1], kS = d.bc[2], kN = d.bc[3];
-    const char* src[NQ];
-    unsigned off[NQ];
-    T add[NQ];
-    bool outflow[NQ];
+    const unsigned pitch = (unsigned)d.pitch;
+    const long long psb = d.ps * (long long)sizeof(S);
+    const float is = d.inv_scale;
+    const T uc = c.uc, inv1uc = c.inv1uc;
+    // additive constants: bounce-back increments bb[side][a] and reflection corrections
+    // dref[a][b] (zero where b == a), addressed per lane as byte offsets into the block
+    const char* cbase = reinterpret_cast<const char*>(&c);
+    constexpr unsigned o_bb = (unsigned)offsetof(Consts<T>, bb);
+    constexpr unsigned o_dr = (unsigned)offsetof(Consts<T>, dref);
+    const char* base = reinterpret_cast<const char*>(fin);
+    // Each direction is resolved (integer arithmetic only) and its two loads, the
+    // population and its additive constant, issued at once; with the outflow memory
+    // below they make one round of loads.
+    T v[NQ], add[NQ];
+    unsigned outflow = 0;  // bit a: direction a takes the convective outflow rule
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
         int si = i - dir_cx(a), sj = j - dir_cy(a);
         int pi = i;  // node whose pull this is (nx - 2 for the outflow's inner value)
-        bool fx = false, fy = false, bb = false, of = false;
-        T bbv = T(0);
+        bool fx = false, fy = false, of = false;
+        int bbside = -1;
         if (si < 0 || si >= nx) {
             const bool west = si < 0;
             const int kind = west ? kW : kE;
@@ -406,11 +417,10 @@ __device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_
                 pi = nx - 2;
                 si = nx - 2 - dir_cx(a);
             } else {  // WALL or VELOCITY: half-way bounce-back at (i, j)
-                bb = true;
-                bbv = west ? uniform_value(c.bb[0][a]) : uniform_value(c.bb[1][a]);
+                bbside = west ? 0 : 1;
             }
         }
-        if (!bb && (sj < 0 || sj >= ny)) {
+        if (bbside < 0 && (sj < 0 || sj >= ny)) {
             const bool south = sj < 0;
             const int kind = south ? kS : kN;
             if (kind == BC_PERIODIC) {
@@ -419,53 +429,45 @@ __device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_
                 fy = true;
                 sj = j;
             } else {
-                bb = true;
-                bbv = south ? uniform_value(c.bb[2][a]) : uniform_value(c.bb[3][a]);
+                bbside = south ? 2 : 3;
             }
         }
         const int ax = dir_flip_x(a), ay = dir_flip_y(a), ao = dir_opp(a);
         int dir;
-        T ad;
-        if (bb) {
+        unsigned to;  // byte offset of the additive constant
+        if (bbside >= 0) {
             dir = ao;
             si = pi;
             sj = j;
-            ad = bbv;
-        } else if (fx && fy) {  // specular reflection between directions
-            dir = ao;
-            ad = uniform_value(c.dref[a][ao]);
-        } else if (fx) {
-            dir = ax;
-            ad = ax != a ? uniform_value(c.dref[a][ax]) : T(0);
-        } else if (fy) {
-            dir = ay;
-            ad = ay != a ? uniform_value(c.dref[a][ay]) : T(0);
+            to = o_bb + (unsigned)(bbside * NQ + a) * (unsigned)sizeof(T);
         } else {
-            dir = a;
-            ad = T(0);
+            dir = (fx && fy) ? ao : (fx ? ax : (fy ? ay : a));  // specular reflection
+            to = o_dr + (unsigned)(a * NQ + dir) * (unsigned)sizeof(T);
         }
-        src[a] = plane<S>(d, fin, dir);
-        off[a] = node_off<S>(d, si, sj);
-        add[a] = ad;
-        outflow[a] = of;
+        v[a] = Codec<S>::load(base + (long long)dir * psb,
+                              ((unsigned)sj * pitch + (unsigned)si) * (unsigned)sizeof(S), is);
+        add[a] = gld(reinterpret_cast<const T*>(cbase + to));
+        if (of) outflow |= 1u << a;
     }
-    T v[NQ];
-#pragma unroll
-    for (int a = 0; a < NQ; ++a) v[a] = Codec<S>::load(src[a], off[a], d.inv_scale);
     const T* outlet = reinterpret_cast<const T*>(outlet_in);
+    T om[3] = {T(0), T(0), T(0)};
+    if (kE == BC_OUTFLOW) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) om[k] = gld(outlet + k * ny + j);
+    }
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
         T x = v[a] + add[a];
         // convective outflow: implicit upwind step of df/dt + U_c df/dx = 0 using last
         // step's value at the east column and this step's value one node in
-        if (outflow[a]) x = (outlet[outflow_slot(a) * ny + j] + c.uc * x) * c.inv1uc;
+        if (outflow & (1u << a)) x = (om[outflow_slot(a)] + uc * x) * inv1uc;
         g[a] = x;
     }
     if (update_outlet && i == nx - 1 && kE == BC_OUTFLOW) {
         T* next = reinterpret_cast<T*>(d.outlet_out);
-        next[0 * ny + j] = g[3];
-        next[1 * ny + j] = g[6];
-        next[2 * ny + j] = g[7];
+        gst(next + 0 * ny + j, g[3]);
+        gst(next + 1 * ny + j, g[6]);
+        gst(next + 2 * ny + j, g[7]);
     }
 }
 
