@@ -710,6 +710,117 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A wave of an interior row (1 <= j <= ny - 2) holding the west node (WEST) or the east
+// node of the row but not both: every lane pulls as in the interior, except that the
+// edge lane takes the three directions whose source lies outside (from x - 1 at the west
+// edge, x + 1 at the east) through that side's rule.  The side, hence its rule and its
+// additive constants, is the same for the whole wave, so the rule costs a few selects
+// and scalar constants instead of the general per-lane resolution.  Lanes beyond the
+// grid (i >= nx) load nothing.
+template <class S, bool WEST>
+__device__ __forceinline__ void pull_xedge(const SimDesc& d,
+                                           const TileScalars<typename Codec<S>::T>& ts, int i,
+                                           int j, typename Codec<S>::T g[NQ],
+                                           bool update_outlet) {
+    using T = typename Codec<S>::T;
+    const Consts<T>& c = consts_of<T>(d);
+    constexpr unsigned e = sizeof(S);
+    const int nx = ts.nx;
+    const int kind = WEST ? d.bc[0] : d.bc[1];
+    // outside directions (source x - 1 at the west edge, x + 1 at the east) and their
+    // rule's replacements: reflected across the side, and reversed (bounce-back)
+    constexpr int A0 = WEST ? 1 : 3, A1 = WEST ? 5 : 6, A2 = WEST ? 8 : 7;
+    const int side = WEST ? 0 : 1;
+    T kadd[3];
+    int kdir[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = k == 0 ? A0 : (k == 1 ? A1 : A2);
+        if (kind == BC_SYMMETRY) {
+            kdir[k] = dir_flip_x(a);
+            kadd[k] = uniform_value(c.dref[a][dir_flip_x(a)]);
+        } else if (kind == BC_WALL || kind == BC_VELOCITY) {
+            kdir[k] = dir_opp(a);
+            kadd[k] = uniform_value(c.bb[side][a]);
+        } else {  // PERIODIC, OUTFLOW: same direction
+            kdir[k] = a;
+            kadd[k] = T(0);
+        }
+    }
+    const bool edge = WEST ? (i == 0) : (i == nx - 1);
+    const unsigned off = ((unsigned)j * (unsigned)ts.pitch + (unsigned)i) * e;
+    const unsigned rowb = ts.rowb;
+    const char* P[NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) P[a] = ts.fin + (long long)a * ts.psb;
+    T v[NQ];
+    if (i < nx) {
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+            const int cx = dir_cx(a), cy = dir_cy(a);
+            unsigned o = off - (unsigned)cx * e - (unsigned)cy * rowb;  // interior source
+            const char* pl = P[a];
+            const int k = a == A0 ? 0 : (a == A1 ? 1 : (a == A2 ? 2 : -1));
+            if (k >= 0 && edge) {
+                if (kind == BC_PERIODIC) {
+                    o = WEST ? o + (unsigned)nx * e : o - (unsigned)nx * e;
+                } else if (kind == BC_SYMMETRY || kind == BC_OUTFLOW) {
+                    o = off - (unsigned)cy * rowb;  // (i, j - cy): the mirror, or node nx - 2's pull
+                    pl = ts.fin + (long long)kdir[k] * ts.psb;
+                } else {  // bounce-back at (i, j)
+                    o = off;
+                    pl = ts.fin + (long long)kdir[k] * ts.psb;
+                }
+            }
+            v[a] = Codec<S>::load(pl, o, ts.inv_scale);
+        }
+    }
+    T om[3] = {T(0), T(0), T(0)};
+    if (!WEST && kind == BC_OUTFLOW && i < nx) {
+        const T* outlet = reinterpret_cast<const T*>(d.outlet);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) om[k] = gld(outlet + k * ts.ny + j);
+    }
+    if (i >= nx) return;
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+        const int k = a == A0 ? 0 : (a == A1 ? 1 : (a == A2 ? 2 : -1));
+        T x = v[a];
+        if (k >= 0 && edge) {
+            x += kadd[k];
+            // convective outflow: implicit upwind step of df/dt + U_c df/dx = 0 using
+            // last step's value at the east column and this step's value one node in
+            if (!WEST && kind == BC_OUTFLOW) x = (om[outflow_slot(a)] + c.uc * x) * c.inv1uc;
+        }
+        g[a] = x;
+    }
+    if (!WEST && update_outlet && edge && kind == BC_OUTFLOW) {
+        T* next = reinterpret_cast<T*>(d.outlet_out);
+        gst(next + 0 * ts.ny + j, g[3]);
+        gst(next + 1 * ts.ny + j, g[6]);
+        gst(next + 2 * ts.ny + j, g[7]);
+    }
+}
+
+// Pull of row j for a wave that holds an edge node: the x-edge path when the row is
+// interior and the wave holds one x edge only, else the general boundary-rule pull.
+template <class S>
+__device__ __forceinline__ void pull_wave_edge(const SimDesc& d,
+                                               const TileScalars<typename Codec<S>::T>& ts,
+                                               int i, int j, typename Codec<S>::T g[NQ]) {
+    const int nx = ts.nx;
+    const int i0 = __builtin_amdgcn_readfirstlane(i - (int)(threadIdx.x & 63));  // wave's first column
+    const bool row_inner = j >= 1 && j <= ts.ny - 2;  // uniform: one row per wave
+    const bool has_w = i0 == 0, has_e = i0 <= nx - 1 && nx - 1 < i0 + 64;
+    if (row_inner && has_w && !has_e) {
+        pull_xedge<S, true>(d, ts, i, j, g, true);
+    } else if (row_inner && has_e && !has_w) {
+        pull_xedge<S, false>(d, ts, i, j, g, true);
+    } else if (i < nx && j < ts.ny) {
+        pull_edge<S>(d, ts.fin, d.outlet, i, j, g, true);
+    }
+}
+
 // ---- one tile of one step ------------------------------------------------------------
 // A tile is TILE_X columns x ROWS rows; each lane walks down its column, issuing the
 // next row's nine loads before colliding the current row.  Nodes are pulled,
@@ -731,8 +842,8 @@ __device__ __forceinline__ void pull_first(const SimDesc& d,
         for (int a = 0; a < NQ; ++a) P[a] = ts.fin + (long long)a * ts.psb;
         pull_interior<S>(P, ((unsigned)j0 * (unsigned)ts.pitch + (unsigned)i) * (unsigned)sizeof(S),
                          ts.rowb, ts.inv_scale, g);
-    } else if (i < ts.nx && j0 < ts.ny) {
-        pull_edge<S>(d, ts.fin, d.outlet, i, j0, g, true);
+    } else {
+        pull_wave_edge<S>(d, ts, i, j0, g);
     }
 }
 
@@ -769,8 +880,8 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
             if (__all(col_inner && j + 1 <= ny - 2))
                 pull_interior<S>(P, ((unsigned)(j + 1) * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S),
                                  rowb, is, gn);
-            else if (col_ok)
-                pull_edge<S>(d, fin, d.outlet, i, j + 1, gn, true);
+            else
+                pull_wave_edge<S>(d, c, i, j + 1, gn);
         }
         if (col_ok) {
             T out[NQ];

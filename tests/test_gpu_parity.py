@@ -200,6 +200,23 @@ def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows):
     g.close()
 
 
+@pytest.mark.parametrize("bcname", list(BCS))
+@pytest.mark.parametrize("nx,ny,rows", [(130, 12, 1), (130, 12, 2), (600, 9, 2)])
+def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows):
+    """Grids wider than a wave: the waves holding the west or the east node of an
+    interior row take the x-edge pull (the east node at 129 sits in a partly filled
+    wave), the first and last rows the general one; every boundary set, rows per tile 1
+    and 2 (the second row's pull comes after the first row's stores), a body near the
+    west edge."""
+    _flush("x-edge %s %dx%d rows %d" % (bcname, nx, ny, rows))
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04,
+                   g=(2e-5, -1e-5) if bcname in ("periodic", "pipe") else (0.0, 0.0))
+    spec["rows_per_tile"] = rows
+    b = W.fixed_disc(5.0, 4.3, ny / 2.0 - 0.3)
+    b.update(vx=0.002, omega=0.001, force_model="vp+mem")
+    run_pair(gpu, spec, b, steps=6, seed=7)
+
+
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
 def test_several_tiles_and_ragged_tail_fp64(gpu, bcname):
     """nx = 600 spans three 256-wide tiles, the last one ragged; the body straddles
