@@ -80,8 +80,8 @@ struct lbm_adjoint {
     void* abar[2] = {nullptr, nullptr};
     void* chibar = nullptr;
     double* tile_acc = nullptr;
-    int* ring_start = nullptr;
-    RingEntry* ring = nullptr;
+    RingSlot* ring = nullptr;
+    int ring_k = 1;
     int* seg_index = nullptr;
     double* red = nullptr;
     int atx = 0;  // adjoint tiles along x (one row per tile)
@@ -157,8 +157,8 @@ void resolve_pull(const int bc[4], int nx, int ny, double uc, int a, int i, int 
 // Readers of every population of the edge nodes: the transpose of the pull there.
 // Every reader of an edge population lies within one node of the edge (or on the
 // opposite edge for periodic sides), so the nodes of the two outer rings are scanned.
-void build_ring(const int bc[4], int nx, int ny, double uc, std::vector<int>& start,
-                std::vector<RingEntry>& ents) {
+void build_ring(const int bc[4], int nx, int ny, double uc, long long ps, int pitch,
+                std::vector<RingSlot>& slots, int& K) {
     const int nr = ring_count(nx, ny);
     std::vector<std::vector<RingEntry>> lists((size_t)nr * NQ);
     std::vector<Src> srcs;
@@ -174,13 +174,16 @@ void build_ring(const int bc[4], int nx, int ny, double uc, std::vector<int>& st
                 }
             }
         }
-    start.assign((size_t)nr * NQ + 1, 0);
-    ents.clear();
-    for (size_t k = 0; k < lists.size(); ++k) {
-        start[k] = (int)ents.size();
-        ents.insert(ents.end(), lists[k].begin(), lists[k].end());
-    }
-    start[lists.size()] = (int)ents.size();
+    // fixed width: K slots per (node, direction), the longest list; the rest padded with
+    // weight 0 (index 0)
+    K = 1;
+    for (const auto& l : lists) K = std::max<int>(K, (int)l.size());
+    slots.assign(lists.size() * (size_t)K, RingSlot{0, 0.0});
+    for (size_t q = 0; q < lists.size(); ++q)
+        for (size_t k = 0; k < lists[q].size(); ++k) {
+            const RingEntry& re = lists[q][k];
+            slots[q * K + k] = RingSlot{(long long)re.a * ps + (long long)re.j * pitch + re.i, re.coef};
+        }
 }
 
 // Pose-dependent parts of the adjoint descriptor.
@@ -248,7 +251,7 @@ void adj_free(lbm_adjoint* A) {
     if (A->sim) (void)hipStreamSynchronize(A->sim->stream);
     void* bufs[] = {A->ad_d, A->seg_descs_d, A->def_pop, A->def_out, A->init_pop, A->init_out,
                     A->ckpt_pop, A->ckpt_out, A->seg_pop, A->seg_out, A->abar[0], A->abar[1],
-                    A->chibar, A->tile_acc, A->ring_start, A->ring, A->seg_index, A->red};
+                    A->chibar, A->tile_acc, A->ring, A->seg_index, A->red};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (A->sim) lbm_destroy(A->sim);
@@ -337,15 +340,10 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
         !alloc((void**)&A->seg_index, 64) || !alloc((void**)&A->red, 8 * sizeof(double)))
         return bail(LBM_ERR_ALLOC);
     // readers of the edge populations
-    std::vector<int> start;
-    std::vector<RingEntry> ents;
-    build_ring(s->desc.bc, nx, ny, o.u_conv, start, ents);
-    if (!alloc((void**)&A->ring_start, start.size() * sizeof(int)) ||
-        !alloc((void**)&A->ring, std::max<size_t>(ents.size(), 1) * sizeof(RingEntry)))
-        return bail(LBM_ERR_ALLOC);
-    hipError_t e = hipMemcpy(A->ring_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !ents.empty())
-        e = hipMemcpy(A->ring, ents.data(), ents.size() * sizeof(RingEntry), hipMemcpyHostToDevice);
+    std::vector<RingSlot> slots;
+    build_ring(s->desc.bc, nx, ny, o.u_conv, s->desc.ps, s->desc.pitch, slots, A->ring_k);
+    if (!alloc((void**)&A->ring, slots.size() * sizeof(RingSlot))) return bail(LBM_ERR_ALLOC);
+    hipError_t e = hipMemcpy(A->ring, slots.data(), slots.size() * sizeof(RingSlot), hipMemcpyHostToDevice);
     // the uniform initial state as lbm_create left it
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e == hipSuccess) e = hipMemcpy(A->def_pop, s->pop[s->host_step & 1], pb, hipMemcpyDeviceToDevice);
@@ -377,8 +375,8 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     ad.abar[1] = A->abar[1];
     ad.chibar = A->chibar;
     ad.tile_acc = A->tile_acc;
-    ad.ring_start = A->ring_start;
     ad.ring = A->ring;
+    ad.ring_k = A->ring_k;
     ad.seg_index = A->seg_index;
     ad.wx = A->wx;
     ad.wy = A->wy;

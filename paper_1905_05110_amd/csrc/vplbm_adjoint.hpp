@@ -41,6 +41,14 @@ struct RingEntry {
     double coef;
 };
 
+// One reader of an edge population in the transposed pull, as the kernel reads it: the
+// element index (plane a, then j * pitch + i) of the reader's adjoint value and the
+// weight of the read.  Unused slots have weight 0 and index 0.
+struct RingSlot {
+    long long idx;
+    double coef;
+};
+
 struct AdjDesc {
     char* seg_pop;          // K + 1 population buffers of a segment, seg_stride bytes apart
     long long seg_stride;
@@ -51,15 +59,14 @@ struct AdjDesc {
     void* abar[2];          // Pbar of the two parities, 9 planes of ps values
     void* chibar;           // dJ/dchi accumulated over the steps, [ny][pitch]
     double* tile_acc;       // per tile of the adjoint grid: u_s adjoint sums (x, y, angular)
-    const int* ring_start;  // CSR over (edge node, direction)
-    const RingEntry* ring;
+    const RingSlot* ring;   // ring_k readers per (edge node, direction)
     int* seg_index;         // segment being reversed (device counter for graph replays)
     double pose[6];         // X, Y, theta, Vx, Vy, Omega
     double wx, wy;          // objective weights
     int box[4];             // adjoint tiles (x range, rows) that may hold chi > 0
     int nbox[4];            // nodes (i0, i1, j0, j1) where d(chi)/d(X, Y) may be non-zero
     long long pop_bytes, out_bytes;
-    int tiles_x, pad;
+    int tiles_x, ring_k;
 };
 
 // Index of an edge node in the ring (bottom row, top row, left column, right column).
@@ -81,6 +88,7 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
     const int i = (int)blockIdx.x * TILE_X + (int)threadIdx.x;
     const int j = (int)blockIdx.y;
     const int nx = d.nx, ny = d.ny;
+    const DiscParams B = disc_params(d.body);  // ahead of the population loads
     const long long ps = d.ps;
     const T* __restrict__ Ain = reinterpret_cast<const T*>(a.abar[(iseg + 1) & 1]);
     T* __restrict__ Aout = reinterpret_cast<T*>(a.abar[iseg & 1]);
@@ -104,7 +112,6 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
             pull_edge<S>(d, fin, outk, i, j, g, false);
         }
         // 2. indicator and rigid velocity at this node
-        const BodyDev& B = *d.body;
         const double rxg = (double)i - a.pose[0], ryg = (double)j - a.pose[1];
         const double chi = B.active ? disc_chi(B, disc_d2(rxg, ryg)) : 0.0;
         const double usx_d = a.pose[3] - a.pose[5] * ryg;
@@ -122,17 +129,25 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
             for (int b = 0; b < NQ; ++b)
                 w[b] = gld(Ain + (long long)b * ps + (o0 + (unsigned)(dir_cy(b) * (int)row + dir_cx(b))));
         } else {
+            // an edge node: the readers of its populations through the boundary rules, ring_k
+            // table slots per direction; slot k of the nine directions is read at once, then
+            // the nine adjoint values it names (two rounds of loads per slot, not two per
+            // reader one after another)
             const int r = ring_index(nx, ny, i, j);
+            const int K = a.ring_k;
+            const RingSlot* rs = a.ring + (long long)r * NQ * K;
 #pragma unroll
-            for (int b = 0; b < NQ; ++b) {
-                T acc = T(0);
-                const int e1 = a.ring_start[r * NQ + b + 1];
-                for (int e = a.ring_start[r * NQ + b]; e < e1; ++e) {
-                    const RingEntry re = a.ring[e];
-                    acc += (T)re.coef *
-                           gld(Ain + (long long)re.a * ps + ((unsigned)re.j * row + (unsigned)re.i));
+            for (int b = 0; b < NQ; ++b) w[b] = T(0);
+            for (int k = 0; k < K; ++k) {
+                long long ix[NQ];
+                T cf[NQ];
+#pragma unroll
+                for (int b = 0; b < NQ; ++b) {
+                    ix[b] = gld(&rs[b * K + k].idx);
+                    cf[b] = (T)gld(&rs[b * K + k].coef);
                 }
-                w[b] = acc;
+#pragma unroll
+                for (int b = 0; b < NQ; ++b) w[b] += cf[b] * gld(Ain + ix[b]);
             }
         }
         // 4. forward node quantities

@@ -497,12 +497,30 @@ __device__ __forceinline__ double disc_d2(double dx, double dy) {
     return a + b;
 }
 
-__device__ __forceinline__ double disc_chi(const BodyDev& B, double d2) {
+template <class Body>
+__device__ __forceinline__ double disc_chi(const Body& B, double d2) {
     if (!B.smooth) return d2 <= B.R2 ? 1.0 : 0.0;
     const double z = (sqrt(d2) - B.R) / B.delta;
     if (z > 20.0) return 0.0;
     if (z < -20.0) return 1.0;
     return 1.0 / (1.0 + exp(2.0 * z));
+}
+
+// The disc's shape parameters, read once (global loads of uniform values: scalar loads
+// when nothing before them may have written the body) rather than through the generic
+// body pointer, whose loads are flat and are waited for with every scalar load after.
+struct DiscParams {
+    int active, smooth;
+    double R, R2, delta;
+};
+__device__ __forceinline__ DiscParams disc_params(const BodyDev* B) {
+    DiscParams q;
+    q.active = gld(&B->active);
+    q.smooth = gld(&B->smooth);
+    q.R = gld(&B->R);
+    q.R2 = gld(&B->R2);
+    q.delta = gld(&B->delta);
+    return q;
 }
 
 // Tile range (inclusive) of the tiles that meet the support of the body; all its
