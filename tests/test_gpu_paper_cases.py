@@ -102,3 +102,45 @@ def test_paper_centred_settling_velocities(gpu):
     # Stokes regime: a lighter and a heavier disc of the same |1 - rho_r| mirror each other
     for a, c in ((0.99, 1.01), (0.98, 1.02), (0.95, 1.05)):
         assert abs(ratio[a] / ratio[c] - 1.0) <= 2e-3
+
+
+def _response(y, y0, D, U0):
+    """Largest |y - y0| / D and the dominant angular frequency omega* = omega D / U0
+    of the displacement over the second half of a run (FFT peak of the Hann-windowed
+    signal, refined by a parabola through the peak and its neighbours)."""
+    a = (y - y0) / D
+    tail = a[len(a) // 2:]
+    x = (tail - tail.mean()) * np.hanning(len(tail))
+    F = np.abs(np.fft.rfft(x))
+    k = int(np.argmax(F[1:])) + 1
+    al, be, ga = F[k - 1], F[k], F[k + 1]
+    f = (k + 0.5 * (al - ga) / (al - 2 * be + ga)) / len(tail)
+    return np.abs(tail).max(), 2 * np.pi * f * D / U0
+
+
+def test_paper_viv_effective_stiffness(gpu):
+    """Sec. 3.3: the paper prints k*_eff = k* - m* omega*^2 for k* = 9, 19, 28 (0.058,
+    3.20, 16.37) and finds lock-in displacements above half a diameter.  m* is not
+    stated; with m* = 9 (from the k* = 28 case, whose response sits at the shedding
+    frequency) the lock-in case k* = 9 is predicted.  At k* = 19, on the edge of lock-in,
+    k*_eff moves by 1 for a 3 % change of the response frequency: bound 1.5 there."""
+    wls = [W.paper_viv(k, storage="fp32") for k in (9.0, 19.0, 28.0)]
+    _flush("paper VIV 1230x410, k* = 9, 19, 28 in one batch, 240000 steps")
+    b = gpu.Batch([(w["spec"], w["body"]) for w in wls], storage="fp32", graph_steps=64)
+    ys = [[] for _ in wls]
+    for _ in range(12):
+        b.step(20000)
+        for i, sm in enumerate(b.sims):
+            ys[i].append(sm.forces()["q"][:, 1].copy())
+    b.close()
+    res = {}
+    for w, yl in zip(wls, ys):
+        amp, om = _response(np.concatenate(yl), w["body"]["y"], w["D"], w["U0"])
+        keff = w["k_star"] - w["m_star"] * om ** 2
+        res[w["k_star"]] = (amp, keff)
+        _flush("k* %g: amplitude %.3f D, omega* %.4f, k*_eff %.3f" % (w["k_star"], amp, om, keff))
+    assert abs(res[9.0][1] - 0.058) <= 0.15
+    assert abs(res[28.0][1] - 16.37) <= 0.3
+    assert abs(res[19.0][1] - 3.20) <= 1.5
+    assert max(res[9.0][0], res[19.0][0]) > 0.5  # lock-in: more than half a diameter
+    assert res[28.0][0] < 0.1  # far from lock-in the displacement stays small
