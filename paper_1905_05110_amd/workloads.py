@@ -163,6 +163,33 @@ def paper_sedimentation_centered(rho_ratio, storage="fp64", D=24.0, Ht=5.0, L=12
                 g=g, dt=dt, dx=dx, kappa=kappa, D=D)
 
 
+def paper_sedimentation_offcentre(storage="fp32", D=31.0, H=125, L=1550, tau=0.6,
+                                  rho_ratio=1.03, D_cm=0.1, mu=0.01, g_cm=980.0,
+                                  x0_D=0.75, y0_D=12.5, force_model="mem"):
+    """The paper's non-centred settling case (Sec. 3.2.2): D = 0.1 cm (31 nodes) in a
+    channel 125 nodes wide and 1550 long, rho_s / rho = 1.03, |g| = 980 cm/s^2, tau = 0.6,
+    released at rest 0.75 D from a side wall and 12.5 D below the top.  The viscosity is
+    taken as 0.01 g/(cm s): with the printed 0.1 the confined Stokes settling velocity
+    gives a particle Reynolds number of 0.1, against the final 8.33 the paper states.  Axes as in paper_sedimentation_centered (channel along x, gravity
+    along +x, closed ends).  The paper gives the particle Reynolds number of the final
+    velocity, 8.33; re_final converts it to a lattice velocity."""
+    nu_l = (tau - 0.5) / 3.0
+    dx = D_cm / D
+    dt = nu_l * dx * dx / mu
+    g = g_cm * dt * dt / dx
+    spec = dict(nx=int(L), ny=int(H), rates=rates_for_tau(tau), eta=ETA, bc=("wall",) * 4,
+                u_wall=[[0.0, 0.0]] * 4, u_conv=0.0, g_fluid=(0.0, 0.0), rho0=1.0,
+                u0=(0.0, 0.0), storage=storage)
+    m = rho_ratio * math.pi * D * D / 4.0
+    y0 = -0.5 + x0_D * D  # from the wall half-way below node 0
+    x0 = -0.5 + y0_D * D
+    body = fixed_disc(D, x0, y0)
+    body.update(mode="free", free_mask=0b111, mass=m, inertia=0.5 * m * (D / 2.0) ** 2,
+                f_ext=(m * (1.0 - 1.0 / rho_ratio) * g, 0.0, 0.0), force_model=force_model)
+    return dict(name="paper_sedimentation_offcentre", spec=spec, body=body, g=g, dt=dt,
+                dx=dx, D=D, nu=nu_l, re_final=8.33)
+
+
 def sedimentation(storage="fp32", nx=1024, ny=4096, D=32.0, x=512.0, y=3800.0, rho_ratio=1.5,
                   tau=0.8, Re_p=1.0):
     """Closed box, disc released from rest, free in x, y and theta under gravity."""

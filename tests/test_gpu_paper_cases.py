@@ -144,3 +144,27 @@ def test_paper_viv_effective_stiffness(gpu):
     assert abs(res[19.0][1] - 3.20) <= 1.5
     assert max(res[9.0][0], res[19.0][0]) > 0.5  # lock-in: more than half a diameter
     assert res[28.0][0] < 0.1  # far from lock-in the displacement stays small
+
+
+def test_paper_offcentre_settling(gpu):
+    """Sec. 3.2.2: a disc released 0.75 D from a wall moves towards the centre line while
+    turning in the positive sense, oscillates briefly about it, and settles there at a
+    final particle Reynolds number of 8.33 (paper).  Channel along x, gravity along +x
+    (a quarter turn of the paper's axes, which keeps the sense of rotation)."""
+    w = W.paper_sedimentation_offcentre(storage="fp32")
+    _flush("paper off-centre settling 1550x125, 100000 steps")
+    g = gpu.Sim(w["spec"], w["body"])
+    g.set_graph_steps(64)
+    r = _run(g, 100000)
+    g.close()
+    yc = (w["spec"]["ny"] - 1) / 2.0
+    D, nu = w["D"], w["nu"]
+    y = r["q"][:, 1] - yc
+    re = r["v"][-5000:, 0].mean() * D / nu
+    _flush("final Re %.3f (paper 8.33); max overshoot %.3f D; final offset %.4f D; first "
+           "rotation %.2e" % (re, y.max() / D, y[-1] / D, r["v"][2000, 2]))
+    assert abs(re / 8.33 - 1.0) <= 0.03
+    assert y[0] < -D  # released near the wall ...
+    assert r["v"][2000, 1] > 0.0 and r["v"][2000, 2] > 0.0  # ... moving off it, turning positively
+    assert y.max() > 0.05 * D  # crosses the centre line once (brief oscillation)
+    assert abs(y[-1]) <= 0.01 * D and abs(r["v"][-1, 2]) <= 1e-6  # settled on the centre line
