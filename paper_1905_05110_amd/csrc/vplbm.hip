@@ -51,6 +51,16 @@ static int upload_desc(lbm_sim* s) {
     return LBM_OK;
 }
 
+// First tile row in dispatch order.  Tiles that meet the body take longer than the
+// others; dispatched among the last workgroups they would extend the end of the grid.
+// Their rows are placed a sixteenth of the grid into the order, not at its start: the
+// rotation is fixed while a captured graph is replayed, and a body that has since moved
+// to lower rows then still has its tiles dispatched early rather than wrapped to the end.
+static int dispatch_row_shift(const int boxM[4], int tiles_y) {
+    const int r = boxM[2] - tiles_y / 16;
+    return ((r % tiles_y) + tiles_y) % tiles_y;
+}
+
 static void drop_graph(lbm_sim* s) {
     if (s->gexec) hipGraphExecDestroy(s->gexec);
     if (s->graph) hipGraphDestroy(s->graph);
@@ -412,8 +422,9 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     st.fresh = 1;
     body_tiles(s->nx, s->ny, s->rows, B, q[0], q[1], st.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
-    if (s->row_shift != st.boxM[2]) {  // captured launches carry the row shift
-        s->row_shift = st.boxM[2];
+    const int shift = dispatch_row_shift(st.boxM, s->desc.tiles_y);
+    if (s->row_shift != shift) {  // captured launches carry the row shift
+        s->row_shift = shift;
         drop_graph(s);
     }
     s->body_h = B;
@@ -624,7 +635,7 @@ static int apply_launch_config(lbm_sim* s, int rows, bool nt) {
     BodyState& st = B.st[s->host_step & 1];
     body_tiles(s->nx, s->ny, rows, B, st.q[0], st.q[1], st.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
-    s->row_shift = st.boxM[2];
+    s->row_shift = dispatch_row_shift(st.boxM, s->desc.tiles_y);
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     int rc = upload_desc(s);
     if (rc) return rc;
@@ -801,7 +812,7 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     BodyDev B;
     std::memcpy(&B, c, sizeof(B));
     s->has_body = B.active != 0;
-    s->row_shift = std::min(std::max(B.st[s->host_step & 1].boxM[2], 0), s->desc.tiles_y - 1);
+    s->row_shift = dispatch_row_shift(B.st[s->host_step & 1].boxM, s->desc.tiles_y);
     if (!s->has_body) s->rec_end = s->drained = std::max(s->drained, s->host_step);
     HIP_TRY(s, hipMemset(s->flag, 0, sizeof(int)));
     drop_graph(s);
@@ -876,15 +887,19 @@ static std::vector<int2> batch_schedule(const lbm_batch* b, int order) {
             for (int i = 0; i < b->n; ++i) {
                 const SimDesc& d = b->sims[i]->desc;
                 if (r >= d.tiles_y) continue;
-                for (int x = 0; x < d.tiles_x; ++x) out.push_back(make_int2(i, (r << 16) | x));
+                for (int x = 0; x < d.tiles_x; ++x)
+                    out.push_back(make_int2(i, (r << 16) | ((x + r) % d.tiles_x)));
             }
         return out;
     }
     for (int i : idx) {
         const SimDesc& d = b->sims[i]->desc;
         for (int r0 = 0; r0 < d.tiles_y; ++r0) {
-            const int r = (r0 + b->sims[i]->row_shift) % d.tiles_y;  // body rows first
-            for (int x = 0; x < d.tiles_x; ++x) out.push_back(make_int2(i, (r << 16) | x));
+            const int r = (r0 + b->sims[i]->row_shift) % d.tiles_y;  // body rows early
+            // columns skewed by the row, as in a single launch: consecutive entries go to
+            // the eight XCDs in turn, and each tile column then visits all of them
+            for (int x = 0; x < d.tiles_x; ++x)
+                out.push_back(make_int2(i, (r << 16) | ((x + r0) % d.tiles_x)));
         }
     }
     return out;

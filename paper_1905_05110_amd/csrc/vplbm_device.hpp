@@ -191,8 +191,11 @@ template <>
 struct Codec<_Float16> {
     using T = float;
     // stored value: round-to-nearest-even of g * 2^k
+    static __device__ __forceinline__ T decode(uint16_t bits, float inv_scale) {
+        return (float)__builtin_bit_cast(_Float16, bits) * inv_scale;
+    }
     static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
-        return (float)*(g_chalf*)(base + off) * inv_scale;
+        return decode(*(g_cu16*)(base + off), inv_scale);
     }
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
@@ -212,9 +215,11 @@ __host__ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 template <>
 struct Codec<bf16s> {
     using T = float;
+    static __device__ __forceinline__ T decode(uint16_t bits, float inv_scale) {
+        return __builtin_bit_cast(float, (uint32_t)bits << 16) * inv_scale;
+    }
     static __device__ __forceinline__ T load(const char* base, unsigned off, float inv_scale) {
-        const uint16_t b = *(g_cu16*)(base + off);
-        return __builtin_bit_cast(float, (uint32_t)b << 16) * inv_scale;
+        return decode(*(g_cu16*)(base + off), inv_scale);
     }
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
@@ -476,15 +481,22 @@ template <class S>
 __device__ __forceinline__ void pull_interior(const char* const P[NQ], unsigned off, unsigned rowb,
                                               float is, typename Codec<S>::T g[NQ]) {
     constexpr unsigned e = sizeof(S);
-    g[0] = Codec<S>::load(P[0], off, is);
-    g[1] = Codec<S>::load(P[1], off - e, is);
-    g[2] = Codec<S>::load(P[2], off - rowb, is);
-    g[3] = Codec<S>::load(P[3], off + e, is);
-    g[4] = Codec<S>::load(P[4], off + rowb, is);
-    g[5] = Codec<S>::load(P[5], off - rowb - e, is);
-    g[6] = Codec<S>::load(P[6], off - rowb + e, is);
-    g[7] = Codec<S>::load(P[7], off + rowb + e, is);
-    g[8] = Codec<S>::load(P[8], off + rowb - e, is);
+    const unsigned o[NQ] = {off,        off - e,           off - rowb,        off + e,          off + rowb,
+                            off - rowb - e, off - rowb + e, off + rowb + e, off + rowb - e};
+    if constexpr (sizeof(S) == 2) {
+        // 16-bit storage: the nine loads are all issued before the first is decoded.
+        // Otherwise the scheduler may place a decode (and its wait) among them, and a
+        // wave then waits for one round trip before issuing its last loads.
+        uint16_t h[NQ];
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) h[a] = *(g_cu16*)(P[a] + o[a]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) g[a] = Codec<S>::decode(h[a], is);
+    } else {
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) g[a] = Codec<S>::load(P[a], o[a], is);
+    }
 }
 
 // ---- indicator function of the disc (Sec. 2.1, Eq. (2)) and rigid velocity ---------
@@ -1138,8 +1150,8 @@ __device__ __forceinline__ void store_state(BodyState& cur, const BodyState& pre
 // needed: the kernel boundary orders producer and consumer (on this multi-XCD part such
 // a fence would write back the whole L2).
 // The caller maps workgroups to tiles (the host rotates the rows so that those of the
-// body come first in dispatch order: their longer work then overlaps the rest of the
-// grid instead of extending the end of the kernel).
+// body are dispatched early, a sixteenth of the grid in: their longer work then overlaps
+// the rest of the grid instead of extending the end of the kernel).
 template <class S, int ROWS, bool NT>
 __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p) {
     using T = typename Codec<S>::T;
@@ -1147,31 +1159,37 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     __shared__ double pose[6];
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
-    // the first row's populations, then the participation box (both parities read, then
-    // selected: no dependent load)
-    // the step's scalars first, then the first row's populations
+    // The step's scalars, then the participation box (both parities read, then selected:
+    // no dependent load), then the first row's populations.
     const TileScalars<T> ts = tile_scalars<S>(d, p);
-    T g[NQ];
-    pull_first<S>(d, ts, tx, ty, ROWS, g);
-    // Then the participation box, as vector-memory (buffer) loads issued behind the
-    // population loads: their wait is counted in order with those, which the collision
-    // waits for anyway.  (Scalar or flat loads ahead of the pull would be waited for,
-    // with every other scalar load, before the population loads are issued.)  The
-    // descriptor covers the two state slots exactly; reads beyond it would return 0.
+    // The box is read with vector-memory (buffer) loads whose values stay in vector
+    // registers until the pull has been issued: a uniform load result is otherwise
+    // moved to scalar registers, with a wait for it, where it is loaded, and a scalar
+    // or flat load would be waited for with every other scalar load.  The wait comes
+    // after the population loads and is counted in order with them, so it costs no
+    // round trip of its own, whatever the pull does with its values.  (The offset's
+    // zero comes from a register the compiler cannot see through, which keeps the
+    // loads per lane.)  The descriptor covers the two state slots exactly; reads
+    // beyond it would return 0.
     const __amdgpu_buffer_rsrc_t bst = __builtin_amdgcn_make_buffer_rsrc(
         (void*)&B.st[0], (short)0, (int)sizeof(B.st), BUFFER_RSRC_WORD3);
-    const int sp = p * (int)sizeof(BodyState), sq = (p ^ 1) * (int)sizeof(BodyState);
+    int vz;
+    asm("v_mov_b32 %0, 0" : "=v"(vz));
+    const int sp = vz + p * (int)sizeof(BodyState), sq = vz + (p ^ 1) * (int)sizeof(BodyState);
     constexpr int o_fresh = (int)offsetof(BodyState, fresh), o_box = (int)offsetof(BodyState, boxM);
-    const int fresh = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_fresh, 0, 0);
+    const int fresh_v = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_fresh, 0, 0);
     int box_p[4], box_q[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         box_p[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_box + 4 * k, 0, 0);
         box_q[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sq + o_box + 4 * k, 0, 0);
     }
+    T g[NQ];
+    pull_first<S>(d, ts, tx, ty, ROWS, g);
+    const int fresh = __builtin_amdgcn_readfirstlane(fresh_v);
     int pb[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pb[k] = fresh ? box_p[k] : box_q[k];
+    for (int k = 0; k < 4; ++k) pb[k] = __builtin_amdgcn_readfirstlane(fresh ? box_p[k] : box_q[k]);
     const int bx0 = pb[0], bx1 = pb[1], by0 = pb[2], by1 = pb[3];
     const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
     double acc[NRED];

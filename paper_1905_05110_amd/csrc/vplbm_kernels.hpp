@@ -29,8 +29,8 @@ struct Launch {
 
 // ---------------------------------------------------------------------------------
 // One kernel serves a single simulation (sched == nullptr, 2D grid of its tiles, tile
-// row (blockIdx.y + row_shift) mod tiles_y) and a batch (1D grid over sched, whose
-// order the host chooses).  The tile body has a single call site, so a simulation
+// row (blockIdx.y + row_shift) mod tiles_y, tile column (blockIdx.x + blockIdx.y) mod
+// tiles_x) and a batch (1D grid over sched, whose order the host chooses).  The tile body has a single call site, so a simulation
 // computes bitwise the same inside a batch as alone.
 // Single-row tiles of 4-byte or narrower storage fit in 64 registers without spilling:
 // eight waves per SIMD then hide more memory latency.
@@ -51,7 +51,12 @@ void k_step(const SimDesc* __restrict__ descs,
         ty = e.y >> 16;
     } else {
         d = descs;
-        tx = (int)blockIdx.x;
+        // Consecutive workgroups go to the eight XCDs in turn.  Skewing the tile column by
+        // the row spreads each column, and so the longer work of the body's tiles, over
+        // all of them instead of one or two.
+        const int gx = (int)gridDim.x;
+        const int t = (int)blockIdx.x + (int)(blockIdx.y % gridDim.x);
+        tx = t >= gx ? t - gx : t;
         ty = (int)blockIdx.y + row_shift;
         if (ty >= (int)gridDim.y) ty -= (int)gridDim.y;
     }
