@@ -205,13 +205,6 @@ struct Codec<_Float16> {
     }
 };
 
-__host__ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 template <>
 struct Codec<bf16s> {
     using T = float;
@@ -224,7 +217,8 @@ struct Codec<bf16s> {
     template <bool NT>
     static __device__ __forceinline__ void store(char* base, unsigned off, T v, float scale) {
         g_u16* q = (g_u16*)(base + off);
-        const uint16_t b = f32_to_bf16_rne(v * scale);
+        // round to nearest even: one conversion instruction on this architecture
+        const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)(v * scale));
         if (NT) __builtin_nontemporal_store(b, q); else *q = b;
     }
 };
