@@ -697,9 +697,9 @@ __device__ __forceinline__ void rk4_dof(double Mq, double cq, double kq, double 
 struct BodyStep {
     double tot[NRED];  // the step's FP64 sums
     double F[3];       // penalization load F_h (x, y and T_h), recorded as fh
-    double q[3], v[3]; // state of the next step
+    double qv[6];      // state of the next step: pose (X, Y, theta), then its velocities
     long long step, t_body;
-    int boxM[4];
+    int boxM[4];       // participation box of that pose (filled by the thread that stores it)
 };
 
 __device__ __forceinline__ bool box_inside(const int a[4], const int b[4]) {
@@ -1088,14 +1088,12 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
                 rk4_dof(k < 2 ? B.mass : B.inertia, B.c[k], B.k[k], B.q0[k], F + B.fext[k], q, v);
             }
         }
-        bs.q[k] = q;
-        bs.v[k] = v;
+        bs.qv[k] = q;
+        bs.qv[3 + k] = v;
     } else if (k == 3) {
         bs.step = step_prev + 1;
         bs.t_body = t_prev + 1;
     }
-    __syncthreads();
-    if (k == 0) body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], bs.boxM);
     __syncthreads();
 }
 
@@ -1124,8 +1122,8 @@ __device__ __forceinline__ void write_record(const SimDesc& d, const BodyState& 
 __device__ __forceinline__ void store_state(BodyState& cur, const BodyState& prev,
                                             const BodyStep& bs, int fresh) {
     for (int k = 0; k < 3; ++k) {
-        cur.q[k] = bs.q[k];
-        cur.v[k] = bs.v[k];
+        cur.q[k] = bs.qv[k];
+        cur.v[k] = bs.qv[3 + k];
         cur.pin_prev[k] = bs.tot[3 + k];
     }
     cur.t_body = bs.t_body;
@@ -1150,7 +1148,7 @@ template <class S, int ROWS, bool NT>
 __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p) {
     using T = typename Codec<S>::T;
     __shared__ double red[NWAVE][NRED];
-    __shared__ double pose[6];
+    __shared__ double pose_set[6];
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
     // The step's scalars, then the participation box (both parities read, then selected:
@@ -1192,19 +1190,20 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
         return;  // uniform over the workgroup
     }
     const bool writer = tx == bx0 && ty == by0;
+    // pose and velocities of this step (LDS): as the host or a flush wrote them, or
+    // derived from the previous step (whose last barrier makes them visible)
+    const double* pose;
     if (fresh) {
         if (threadIdx.x < 3) {
-            pose[threadIdx.x] = B.st[p].q[threadIdx.x];
-            pose[3 + threadIdx.x] = B.st[p].v[threadIdx.x];
+            pose_set[threadIdx.x] = B.st[p].q[threadIdx.x];
+            pose_set[3 + threadIdx.x] = B.st[p].v[threadIdx.x];
         }
+        __syncthreads();
+        pose = pose_set;
     } else {
         derive_body(d, p, red, bs);
-        if (threadIdx.x < 3) {
-            pose[threadIdx.x] = bs.q[threadIdx.x];
-            pose[3 + threadIdx.x] = bs.v[threadIdx.x];
-        }
+        pose = bs.qv;
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
     step_rows<S, ROWS, NT, true>(d, ts, tx, ty, acc, pose, g);
@@ -1240,8 +1239,9 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
         if (!fresh) {
             const BodyState& prev = B.st[p ^ 1];
             int exact[4];
-            body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], exact, 1.0);
+            body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], exact, 1.0);
             if (!box_inside(exact, pb)) raise_flag(d.flag, 2);  // moved >= 2 nodes in a step
+            body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], bs.boxM);
             write_record(d, prev, bs);
             store_state(B.st[p], prev, bs, 0);
         }
@@ -1261,8 +1261,9 @@ __device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
     if (threadIdx.x == 0) {
         const BodyState& prev = B.st[p ^ 1];
         int exact[4];
-        body_tiles(d.nx, d.ny, d.rows, B, bs.q[0], bs.q[1], exact, 1.0);
+        body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], exact, 1.0);
         if (!box_inside(exact, prev.boxM)) raise_flag(d.flag, 2);
+        body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], bs.boxM);
         write_record(d, prev, bs);
         store_state(B.st[p], prev, bs, 1);
     }
