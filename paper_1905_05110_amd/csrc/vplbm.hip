@@ -284,6 +284,39 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
                     : 0.0;
             cd.bb[side][a] = moving + cd.dref[a][dir_opp(a)];
         }
+    // the x-edge rules of the west and east sides for their three outside directions
+    for (int side = 0; side < 2; ++side)
+        for (int k = 0; k < 3; ++k) {
+            const int a = side == 0 ? (k == 0 ? 1 : (k == 1 ? 5 : 8)) : (k == 0 ? 3 : (k == 1 ? 6 : 7));
+            const int cx = dir_cx(a), cy = dir_cy(a);
+            int* src = d.xsrc[side][k];
+            double add = 0.0;
+            switch (o.bc[side]) {
+                case LBM_BC_PERIODIC:  // the node across the domain
+                    src[0] = -cx + (side == 0 ? nx : -nx);
+                    src[1] = -cy;
+                    src[2] = a;
+                    break;
+                case LBM_BC_SYMMETRY:  // the mirror image (i, j - cy), reflected direction
+                    src[0] = 0;
+                    src[1] = -cy;
+                    src[2] = dir_flip_x(a);
+                    add = cd.dref[a][dir_flip_x(a)];
+                    break;
+                case LBM_BC_OUTFLOW:  // node nx - 2's pull of the same direction
+                    src[0] = 0;
+                    src[1] = -cy;
+                    src[2] = a;
+                    break;
+                default:  // bounce-back at the node itself
+                    src[0] = 0;
+                    src[1] = 0;
+                    src[2] = dir_opp(a);
+                    add = cd.bb[side][a];
+                    break;
+            }
+            cd.xadd[side][k] = add;
+        }
     Consts<float>& cf = d.cf;
     {
         const double* src = reinterpret_cast<const double*>(&cd);

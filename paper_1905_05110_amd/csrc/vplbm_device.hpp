@@ -109,6 +109,8 @@ struct Consts {
     T uc, inv1uc;                 // convective outflow velocity, 1/(1 + U_c)
     T bb[4][NQ];                  // bounce-back increment per side and direction
     T dref[NQ][NQ];               // f_ref[b] - f_ref[a]: correction when a pulls b
+    T xadd[2][3];                 // x-edge rule (west, east) for the three directions whose
+                                  // source lies outside: the additive constant
 };
 
 struct SimDesc {
@@ -123,6 +125,9 @@ struct SimDesc {
     long long ps;        // plane stride (elements)
     int nx, ny, pitch, rows, tiles_x, tiles_y, hist_cap, pad;
     int bc[4];
+    // x-edge rule (west, east) for the three directions whose source lies outside (1, 5, 8
+    // at the west side, 3, 6, 7 at the east): source (i + dx, j + dy) and its plane
+    int xsrc[2][3][3];
     double u0x, u0y;     // reference velocity u_ref of the offsets
     double fref[NQ];     // f_eq(1, u_ref)
     float scale, inv_scale;  // storage scale of 16-bit offsets
@@ -750,26 +755,21 @@ __device__ __forceinline__ void pull_xedge(const SimDesc& d,
     const Consts<T>& c = consts_of<T>(d);
     constexpr unsigned e = sizeof(S);
     const int nx = ts.nx;
-    const int kind = WEST ? d.bc[0] : d.bc[1];
-    // outside directions (source x - 1 at the west edge, x + 1 at the east) and their
-    // rule's replacements: reflected across the side, and reversed (bounce-back)
+    // outside directions (source x - 1 at the west edge, x + 1 at the east); the side's
+    // rule for them (periodic wrap, reflection across the side, bounce-back, or the
+    // outflow's value one node in) was resolved on the host into a source offset, a
+    // plane and an additive constant, all read here in one round of scalar loads
     constexpr int A0 = WEST ? 1 : 3, A1 = WEST ? 5 : 6, A2 = WEST ? 8 : 7;
     const int side = WEST ? 0 : 1;
+    const int kind = d.bc[side];
     T kadd[3];
-    int kdir[3];
+    int sdx[3], sdy[3], spl[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const int a = k == 0 ? A0 : (k == 1 ? A1 : A2);
-        if (kind == BC_SYMMETRY) {
-            kdir[k] = dir_flip_x(a);
-            kadd[k] = uniform_value(c.dref[a][dir_flip_x(a)]);
-        } else if (kind == BC_WALL || kind == BC_VELOCITY) {
-            kdir[k] = dir_opp(a);
-            kadd[k] = uniform_value(c.bb[side][a]);
-        } else {  // PERIODIC, OUTFLOW: same direction
-            kdir[k] = a;
-            kadd[k] = T(0);
-        }
+        sdx[k] = d.xsrc[side][k][0];
+        sdy[k] = d.xsrc[side][k][1];
+        spl[k] = d.xsrc[side][k][2];
+        kadd[k] = c.xadd[side][k];
     }
     const bool edge = WEST ? (i == 0) : (i == nx - 1);
     const unsigned off = ((unsigned)j * (unsigned)ts.pitch + (unsigned)i) * e;
@@ -786,15 +786,8 @@ __device__ __forceinline__ void pull_xedge(const SimDesc& d,
             const char* pl = P[a];
             const int k = a == A0 ? 0 : (a == A1 ? 1 : (a == A2 ? 2 : -1));
             if (k >= 0 && edge) {
-                if (kind == BC_PERIODIC) {
-                    o = WEST ? o + (unsigned)nx * e : o - (unsigned)nx * e;
-                } else if (kind == BC_SYMMETRY || kind == BC_OUTFLOW) {
-                    o = off - (unsigned)cy * rowb;  // (i, j - cy): the mirror, or node nx - 2's pull
-                    pl = ts.fin + (long long)kdir[k] * ts.psb;
-                } else {  // bounce-back at (i, j)
-                    o = off;
-                    pl = ts.fin + (long long)kdir[k] * ts.psb;
-                }
+                o = off + (unsigned)(sdx[k] * (int)e) + (unsigned)sdy[k] * rowb;
+                pl = ts.fin + (long long)spl[k] * ts.psb;
             }
             v[a] = Codec<S>::load(pl, o, ts.inv_scale);
         }
