@@ -161,7 +161,6 @@ typedef __attribute__((address_space(1))) const double g_cdouble;
 typedef __attribute__((address_space(1))) double g_double;
 typedef __attribute__((address_space(1))) const float g_cfloat;
 typedef __attribute__((address_space(1))) float g_float;
-typedef __attribute__((address_space(1))) const _Float16 g_chalf;
 typedef __attribute__((address_space(1))) _Float16 g_half;
 typedef __attribute__((address_space(1))) const uint16_t g_cu16;
 typedef __attribute__((address_space(1))) uint16_t g_u16;
@@ -358,14 +357,6 @@ __device__ bool pull_rules(const SimDesc& d, const void* fin, int a, int i, int 
 // Index of a direction in the 3-slot outflow memory (directions 3, 6, 7).
 __device__ __forceinline__ int outflow_slot(int a) { return a == 3 ? 0 : (a == 6 ? 1 : 2); }
 
-// Pulled offsets of a node on the domain edge, through the boundary rules; outlet_in
-// is the outflow memory of the previous step.  The source of every direction is
-// resolved first (pure arithmetic: the rules of pull_rules, with the convective outflow
-// reading its value one node in), then the nine loads are issued together, so an edge
-// node costs one memory round trip like an interior one.  When update_outlet is set,
-// the east column stores its pulled values 3, 6, 7 into d.outlet_out as the memory of
-// the next step (in place when outlet_out == outlet_in: each element is read and
-// written by the same thread).
 // A uniform value held in a scalar register.  Selecting between two such values keeps
 // the choice in registers; selecting between two loads would let the compiler turn it
 // into one load from a per-lane address, a memory round trip on the critical path.
@@ -379,6 +370,14 @@ __device__ __forceinline__ double uniform_value(double x) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Pulled offsets of a node on the domain edge, through the boundary rules; outlet_in
+// is the outflow memory of the previous step.  The source of every direction is
+// resolved first (pure arithmetic: the rules of pull_rules, with the convective outflow
+// reading its value one node in), then the nine loads are issued together, so an edge
+// node costs one memory round trip like an interior one.  When update_outlet is set,
+// the east column stores its pulled values 3, 6, 7 into d.outlet_out as the memory of
+// the next step (in place when outlet_out == outlet_in: each element is read and
+// written by the same thread).
 template <class S>
 __device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_in, int i, int j,
                           typename Codec<S>::T g[NQ], bool update_outlet) {
