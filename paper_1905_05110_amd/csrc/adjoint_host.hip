@@ -81,6 +81,7 @@ struct lbm_adjoint {
     void* chibar = nullptr;
     double* tile_acc = nullptr;
     RingSlot* ring = nullptr;
+    int* ring_kn = nullptr;  // per edge node: its longest reader list (slots it must visit)
     int ring_k = 1;
     int* seg_index = nullptr;
     double* red = nullptr;
@@ -158,7 +159,7 @@ void resolve_pull(const int bc[4], int nx, int ny, double uc, int a, int i, int 
 // Every reader of an edge population lies within one node of the edge (or on the
 // opposite edge for periodic sides), so the nodes of the two outer rings are scanned.
 void build_ring(const int bc[4], int nx, int ny, double uc, long long ps, int pitch,
-                std::vector<RingSlot>& slots, int& K) {
+                std::vector<RingSlot>& slots, std::vector<int>& kn, int& K) {
     const int nr = ring_count(nx, ny);
     std::vector<std::vector<RingEntry>> lists((size_t)nr * NQ);
     std::vector<Src> srcs;
@@ -178,6 +179,10 @@ void build_ring(const int bc[4], int nx, int ny, double uc, long long ps, int pi
     // weight 0 (index 0)
     K = 1;
     for (const auto& l : lists) K = std::max<int>(K, (int)l.size());
+    // slots an edge node visits: its longest list over the nine directions (at least one)
+    kn.assign((size_t)nr, 1);
+    for (int r = 0; r < nr; ++r)
+        for (int a = 0; a < NQ; ++a) kn[r] = std::max<int>(kn[r], (int)lists[(size_t)r * NQ + a].size());
     slots.assign(lists.size() * (size_t)K, RingSlot{0, 0.0});
     for (size_t q = 0; q < lists.size(); ++q)
         for (size_t k = 0; k < lists[q].size(); ++k) {
@@ -251,7 +256,7 @@ void adj_free(lbm_adjoint* A) {
     if (A->sim) (void)hipStreamSynchronize(A->sim->stream);
     void* bufs[] = {A->ad_d, A->seg_descs_d, A->def_pop, A->def_out, A->init_pop, A->init_out,
                     A->ckpt_pop, A->ckpt_out, A->seg_pop, A->seg_out, A->abar[0], A->abar[1],
-                    A->chibar, A->tile_acc, A->ring, A->seg_index, A->red};
+                    A->chibar, A->tile_acc, A->ring, A->ring_kn, A->seg_index, A->red};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (A->sim) lbm_destroy(A->sim);
@@ -341,9 +346,13 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
         return bail(LBM_ERR_ALLOC);
     // readers of the edge populations
     std::vector<RingSlot> slots;
-    build_ring(s->desc.bc, nx, ny, o.u_conv, s->desc.ps, s->desc.pitch, slots, A->ring_k);
-    if (!alloc((void**)&A->ring, slots.size() * sizeof(RingSlot))) return bail(LBM_ERR_ALLOC);
+    std::vector<int> kn;
+    build_ring(s->desc.bc, nx, ny, o.u_conv, s->desc.ps, s->desc.pitch, slots, kn, A->ring_k);
+    if (!alloc((void**)&A->ring, slots.size() * sizeof(RingSlot)) ||
+        !alloc((void**)&A->ring_kn, kn.size() * sizeof(int)))
+        return bail(LBM_ERR_ALLOC);
     hipError_t e = hipMemcpy(A->ring, slots.data(), slots.size() * sizeof(RingSlot), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(A->ring_kn, kn.data(), kn.size() * sizeof(int), hipMemcpyHostToDevice);
     // the uniform initial state as lbm_create left it
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e == hipSuccess) e = hipMemcpy(A->def_pop, s->pop[s->host_step & 1], pb, hipMemcpyDeviceToDevice);
@@ -376,6 +385,7 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     ad.chibar = A->chibar;
     ad.tile_acc = A->tile_acc;
     ad.ring = A->ring;
+    ad.ring_kn = A->ring_kn;
     ad.ring_k = A->ring_k;
     ad.seg_index = A->seg_index;
     ad.wx = A->wx;

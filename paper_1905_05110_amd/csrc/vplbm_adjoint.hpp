@@ -60,6 +60,7 @@ struct AdjDesc {
     void* chibar;           // dJ/dchi accumulated over the steps, [ny][pitch]
     double* tile_acc;       // per tile of the adjoint grid: u_s adjoint sums (x, y, angular)
     const RingSlot* ring;   // ring_k readers per (edge node, direction)
+    const int* ring_kn;     // per edge node: the slots it visits (its longest list)
     int* seg_index;         // segment being reversed (device counter for graph replays)
     double pose[6];         // X, Y, theta, Vx, Vy, Omega
     double wx, wy;          // objective weights
@@ -136,9 +137,13 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
             const int r = ring_index(nx, ny, i, j);
             const int K = a.ring_k;
             const RingSlot* rs = a.ring + (long long)r * NQ * K;
+            // slots beyond the node's longest list hold weight 0 and are not visited (the
+            // count is read with the first slot; every list has at least one slot)
+            const int kn = gld(a.ring_kn + r);
 #pragma unroll
             for (int b = 0; b < NQ; ++b) w[b] = T(0);
             for (int k = 0; k < K; ++k) {
+                if (k > 0 && k >= kn) break;
                 long long ix[NQ];
                 T cf[NQ];
 #pragma unroll
