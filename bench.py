@@ -50,6 +50,8 @@ def parse():
                     help="steps per captured HIP graph in the timed region (0: eager launches)")
     ap.add_argument("--rows", type=int, default=0, help="rows per tile (0: autotune)")
     ap.add_argument("--store", default="auto", choices=("auto", "plain", "nontemporal"))
+    ap.add_argument("--tile-width", type=int, default=0, choices=(0, 256, 512),
+                    help="columns per tile (0: autotune)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -99,18 +101,18 @@ def kernel_source_hash(storage):
     return h.hexdigest()[:16]
 
 
-def traffic_for(path, storage, nx, ny, rows, nt):
+def traffic_for(path, storage, nx, ny, rows, nt, tile):
     """Measured HBM bytes per launch from the rocprofv3 counter summary, if one was
     recorded for this configuration and for the kernel sources as they are now."""
     if not path or not os.path.exists(path):
         return None
-    want = "%s %d %d %s %d" % (storage, nx, ny, rows, int(bool(nt)))
+    want = "%s %d %d %d %d %d" % (storage, nx, ny, rows, int(bool(nt)), tile)
     src = kernel_source_hash(storage)
     for line in open(path):
         f = line.split()
-        # traffic <storage> <nx> <ny> <rows> <nt> <source-hash> <bytes-per-launch>
-        if len(f) == 8 and f[0] == "traffic" and " ".join(f[1:6]) == want and f[6] == src:
-            return int(f[7])
+        # traffic <storage> <nx> <ny> <rows> <nt> <tile> <source-hash> <bytes-per-launch>
+        if len(f) == 9 and f[0] == "traffic" and " ".join(f[1:7]) == want and f[7] == src:
+            return int(f[8])
     return None
 
 
@@ -192,15 +194,17 @@ def run_batch(args):
     with torch.cuda.stream(stream):
         rows = args.rows if args.rows else 0
         batch = vplbm.Batch(members, storage=args.storage, rows=rows, store=args.store,
-                            history_cap=4096, stream=stream.cuda_stream)
+                            history_cap=4096, stream=stream.cuda_stream,
+                            tile_width=args.tile_width)
         tuned = None
         w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
         print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
         batch.step(w_pre)
         batch.sync()
-        if not args.no_autotune and args.rows == 0 and args.store == "auto":
+        if not args.no_autotune and args.rows == 0 and args.store == "auto" and not args.tile_width:
             print("autotune", file=sys.stderr, flush=True)
             tuned = batch.autotune(trial_steps=20)
+        b_rows, b_nt, b_tile = batch.sims[0].launch_config()
         if args.graph_steps:
             batch.set_graph_steps(args.graph_steps)
         batch.step(w_post)
@@ -233,8 +237,8 @@ def run_batch(args):
         "data": "synthetic (lattice flows from a uniform inflow state; no dataset)",
         "config": {"workload": "batch_sweep_64", "runs": len(members), "nodes": nodes,
                    "storage": args.storage, "graph_steps": args.graph_steps,
-                   "rows_per_tile": tuned[0] if tuned else args.rows,
-                   "nontemporal_stores": bool(tuned[1]) if tuned else args.store,
+                   "rows_per_tile": b_rows, "nontemporal_stores": bool(b_nt),
+                   "tile_width": b_tile,
                    "order": order_names[tuned[2]] if tuned else "largest_first"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -350,7 +354,8 @@ def main():
     from paper_1905_05110_amd import vplbm
 
     wl = W.free_viv(storage=args.storage)
-    spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store)
+    spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store,
+                tile_width=args.tile_width)
     body = wl["body"]
     nodes = spec["nx"] * spec["ny"]
     if args.copy_calibration:
@@ -367,10 +372,10 @@ def main():
         print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
         sim.step(w_pre)
         sim.sync()
-        if not args.no_autotune and args.rows == 0 and args.store == "auto":
+        if not args.no_autotune and args.rows == 0 and args.store == "auto" and not args.tile_width:
             print("autotune", file=sys.stderr, flush=True)
             tuned = sim.autotune(trial_steps=50)
-        rows, nt = (tuned[0], tuned[1]) if tuned else (None, None)
+        rows, nt, tile = sim.launch_config()
         if args.graph_steps:
             sim.set_graph_steps(args.graph_steps)
         sim.step(w_post)
@@ -409,12 +414,11 @@ def main():
         "config": {"workload": "free_viv_2048x1024", "nx": spec["nx"], "ny": spec["ny"],
                    "storage": args.storage, "body": "disc D=40, free in y, mass ratio 10, U_r 5",
                    "Re": 150, "graph_steps": args.graph_steps,
-                   "rows_per_tile": rows if rows else args.rows,
-                   "nontemporal_stores": bool(nt) if nt is not None else args.store},
+                   "rows_per_tile": rows, "nontemporal_stores": bool(nt), "tile_width": tile},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_for(args.traffic, args.storage, spec["nx"], spec["ny"],
-                                            rows, nt),
+                                            rows, nt, tile),
                      "kernel": "k_step<%s>" % args.storage,
                      "avg_kernel_us": round(avg_kernel_s * 1e6, 3),
                      "algorithmic_bytes_per_launch": bytes_per_launch},

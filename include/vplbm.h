@@ -126,7 +126,7 @@ typedef struct {
     int fp16_scale_log2;   /* k of the FP16 offset scale 2^k, 0..14 (default 10) */
     int history_cap;       /* force records kept on the device between drains (default 65536) */
     int offset_ref;        /* LBM_REF_INITIAL (default) or LBM_REF_REST */
-    int rows_per_tile;     /* grid rows per 256-column tile (nodes per lane): 1, 2, 4;
+    int rows_per_tile;     /* grid rows per tile (nodes per lane): 1, 2, 4;
                               0 = default (1).  Each setting is deterministic; results of
                               different settings agree to rounding (kernel variants may
                               contract multiply-adds differently; FP64 force sums follow
@@ -135,6 +135,10 @@ typedef struct {
     void* hip_stream;      /* hipStream_t to run on; NULL: the library creates one */
     void* pop_buffers[2];  /* optional caller-owned device buffers of lbm_pop_bytes() each */
     int collision;         /* LBM_COLLIDE_MRT (default) or LBM_COLLIDE_BGK */
+    int tile_width;        /* grid columns per tile (threads per workgroup of the step
+                              kernel): 0 = default (256), 256 or 512.  Like rows_per_tile
+                              a launch choice: results of different settings agree to
+                              rounding (the FP64 force sums follow the tile order). */
 } lbm_opts;
 
 typedef struct {
@@ -238,7 +242,8 @@ int64_t lbm_step_index(const lbm_sim* sim);
 int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms);
 
 /* Chooses the launch configuration of the step kernel (rows per tile 1/2/4, plain or
- * nontemporal stores) by timing trial_steps steps of each candidate on a scratch
+ * nontemporal stores, 256 or 512 columns per tile) by timing trial_steps steps of each
+ * candidate on a scratch
  * simulation of the same grid, storage and body, started from a copy of sim's current
  * populations and outflow memory (call it once the flow has developed: the uniform
  * start state is exactly zero in offsets and moves faster than a developed flow), and
@@ -248,6 +253,11 @@ int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms
  * the measured time per step in microseconds (-1 when taken from the cache). */
 int lbm_autotune(lbm_sim* sim, int trial_steps, const char* cache_path, int* rows_out,
                  int* nt_out, double* us_out);
+
+/* The launch configuration in use (set at creation, by lbm_autotune, or for a batch
+ * member by the batch): rows per tile, nontemporal-store flag, columns per tile.
+ * Outputs may be NULL. */
+int lbm_launch_config(const lbm_sim* sim, int* rows_out, int* nt_out, int* tile_width_out);
 
 /* Serialises the full state (populations, outflow memory, body, step index) into a
  * host buffer; with buf NULL only *size_out is set.  lbm_load restores a state saved
@@ -282,6 +292,7 @@ typedef struct {
     int store_mode;     /* LBM_STORE_* */
     int order;          /* LBM_ORDER_* */
     void* hip_stream;   /* NULL: the library creates one */
+    int tile_width;     /* 0 (default: 256), 256 or 512 */
 } lbm_batch_opts;
 
 void lbm_default_batch_opts(lbm_batch_opts* o);
@@ -306,11 +317,13 @@ int lbm_batch_sync(lbm_batch* batch);
 int lbm_batch_sim(lbm_batch* batch, int i, lbm_sim** out);
 int lbm_batch_size(const lbm_batch* batch);
 
-/* Sets the launch configuration: rows 1/2/4, LBM_STORE_PLAIN or _NONTEMPORAL, order. */
+/* Sets the launch configuration: rows 1/2/4, LBM_STORE_PLAIN or _NONTEMPORAL, order
+ * (the columns per tile stay as they are). */
 int lbm_batch_configure(lbm_batch* batch, int rows, int store_mode, int order);
 
-/* Chooses rows, store mode and order by timing trial_steps steps of each candidate on a
- * scratch copy of the batch, then applies them (members' states are not touched).
+/* Chooses rows, store mode, columns per tile and order by timing trial_steps steps of
+ * each candidate on a scratch copy of the batch, then applies them (members' states are
+ * not touched; lbm_launch_config on a member reports the choice).
  * Outputs may be NULL; us_out is the time per batch step in microseconds. */
 int lbm_batch_autotune(lbm_batch* batch, int trial_steps, int* rows_out, int* nt_out,
                        int* order_out, double* us_out);

@@ -203,7 +203,7 @@ void set_pose(lbm_adjoint* A) {
     ad.pose[5] = b.omega;
     const BodyDev& B = A->sim->body_h;
     int nb[4];
-    body_tiles(A->nx, A->ny, 1, B, b.x, b.y, nb, 1.0);  // rows of one node: tile rows = rows
+    body_tiles(A->nx, A->ny, 1, TILE_X, B, b.x, b.y, nb, 1.0);  // adjoint tiles: one row each
     ad.box[0] = nb[0];
     ad.box[1] = nb[1];
     ad.box[2] = nb[2];
@@ -240,7 +240,8 @@ int enqueue_segment(lbm_adjoint* A) {
     dispatch(A->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         for (int i = 0; i < A->K; ++i)
-            Launch<S>::step(A->seg_descs_d + i, fgrid, s->rows, s->nt, i & 1, s->stream, s->row_shift);
+            Launch<S>::step(A->seg_descs_d + i, fgrid, s->rows, s->nt, s->desc.tile_w, i & 1, s->stream,
+                            s->row_shift);
         if constexpr (std::is_same_v<S, double> || std::is_same_v<S, float>)
             for (int i = A->K - 1; i >= 0; --i) AdjLaunch<S>::step(s->desc_d, A->ad_d, agrid, i, s->stream);
         return 0;
@@ -599,7 +600,7 @@ int lbm_adjoint_time_kernels(lbm_adjoint* A, int reps, double* adjoint_us, doubl
             (void)hipEventRecord(e[1], s->stream);
             for (int k = 0; k < reps; ++k) {
                 const int i = k % A->K;
-                Launch<S>::step(A->seg_descs_d + i, fgrid, s->rows, s->nt, i & 1, s->stream,
+                Launch<S>::step(A->seg_descs_d + i, fgrid, s->rows, s->nt, s->desc.tile_w, i & 1, s->stream,
                                 s->row_shift);
             }
         }

@@ -75,7 +75,7 @@ static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nu
     if (ev0) HIP_TRY(s, hipEventRecord(ev0, s->stream));
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, p, s->stream, s->row_shift);
+        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, s->desc.tile_w, p, s->stream, s->row_shift);
         return LBM_OK;
     });
     if (ev1) HIP_TRY(s, hipEventRecord(ev1, s->stream));
@@ -137,6 +137,8 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
     if (o.rows_per_tile != 0 && o.rows_per_tile != 1 && o.rows_per_tile != 2 &&
         o.rows_per_tile != 4)
         return m = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
+    if (o.tile_width != 0 && o.tile_width != TILE_X && o.tile_width != TILE_WIDE)
+        return m = "tile_width must be 0, 256 or 512", LBM_ERR_ARG;
     if (o.collision != LBM_COLLIDE_MRT && o.collision != LBM_COLLIDE_BGK)
         return m = "collision must be LBM_COLLIDE_MRT or LBM_COLLIDE_BGK", LBM_ERR_ARG;
     if (o.store_mode < LBM_STORE_AUTO || o.store_mode > LBM_STORE_NONTEMPORAL)
@@ -223,9 +225,10 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     s->rows = o.rows_per_tile ? o.rows_per_tile : 1;
     s->nt = o.store_mode == LBM_STORE_NONTEMPORAL ||
             (o.store_mode == LBM_STORE_AUTO && 2 * s->pop_bytes > (size_t(1) << 30));
-    const int tiles_x = (nx + TILE_X - 1) / TILE_X;
+    const int tile_w = o.tile_width ? o.tile_width : TILE_X;
+    const int tiles_x = (nx + tile_w - 1) / tile_w;
     const int tiles_y = (ny + s->rows - 1) / s->rows;
-    const int ntiles = tiles_x * ny;  // enough slots for any rows per tile
+    const int ntiles = (nx + TILE_X - 1) / TILE_X * ny;  // enough slots for any tile shape
     CREATE_TRY(hipMalloc(&s->outlet, 3 * (size_t)ny * tsz));
     CREATE_TRY(hipMalloc((void**)&s->body_d, sizeof(BodyDev)));
     CREATE_TRY(hipMalloc((void**)&s->partials, 2 * (size_t)ntiles * NRED * sizeof(double)));
@@ -250,6 +253,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.pitch = row_pitch(nx);
     d.rows = s->rows;
     d.tiles_x = tiles_x;
+    d.tile_w = tile_w;
     d.tiles_y = tiles_y;
     d.hist_cap = s->hist_cap;
     for (int k = 0; k < 4; ++k) d.bc[k] = o.bc[k];
@@ -453,8 +457,11 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     st.step = s->host_step;
     st.pin_valid = 0;
     st.fresh = 1;
-    body_tiles(s->nx, s->ny, s->rows, B, q[0], q[1], st.boxM);
+    body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, B, q[0], q[1], st.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
+    // a step takes part by the box of the state before it: the other slot starts as a
+    // copy of this one
+    B.st[p ^ 1] = st;
     const int shift = dispatch_row_shift(st.boxM, s->desc.tiles_y);
     if (s->row_shift != shift) {  // captured launches carry the row shift
         s->row_shift = shift;
@@ -479,7 +486,7 @@ int lbm_clear_body(lbm_sim* s) {
     BodyState& st = B.st[p];
     st.pin_valid = 0;
     st.fresh = 1;
-    for (int k = 0; k < 4; ++k) st.boxM[k] = st.part_box[k] = 0;
+    for (int k = 0; k < 4; ++k) st.boxM[k] = st.part_box[k] = B.st[p ^ 1].boxM[k] = 0;
     if (s->row_shift != 0) {
         s->row_shift = 0;
         drop_graph(s);
@@ -656,18 +663,24 @@ int lbm_get_body_state(lbm_sim* s, double* q, double* v) {
 }
 
 // ---- launch configuration and its autotuning ---------------------------------------
-static int apply_launch_config(lbm_sim* s, int rows, bool nt) {
+static int apply_launch_config(lbm_sim* s, int rows, bool nt, int tile_w) {
     int rc0 = sync_check(s);  // the next step's state is then fresh
     if (rc0 && rc0 != LBM_ERR_UNSTABLE) return rc0;
     s->rows = rows;
     s->nt = nt;
     s->desc.rows = rows;
     s->desc.tiles_y = (s->ny + rows - 1) / rows;
+    s->desc.tile_w = tile_w;
+    s->desc.tiles_x = (s->nx + tile_w - 1) / tile_w;
     BodyDev B;
     HIP_TRY(s, hipMemcpy(&B, s->body_d, sizeof(B), hipMemcpyDeviceToHost));
+    // the boxes of the final state and of the one before it (by which the next step takes
+    // part), in the new tiles
     BodyState& st = B.st[s->host_step & 1];
-    body_tiles(s->nx, s->ny, rows, B, st.q[0], st.q[1], st.boxM);
-    for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
+    BodyState& before = B.st[(s->host_step & 1) ^ 1];
+    body_tiles(s->nx, s->ny, rows, tile_w, B, st.q[0], st.q[1], st.boxM);
+    body_tiles(s->nx, s->ny, rows, tile_w, B, before.q[0], before.q[1], before.boxM);
+    for (int k = 0; k < 4; ++k) st.part_box[k] = before.boxM[k];
     s->row_shift = dispatch_row_shift(st.boxM, s->desc.tiles_y);
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     int rc = upload_desc(s);
@@ -690,21 +703,31 @@ static std::string tune_key(const lbm_sim* s) {
     return buf;
 }
 
-// Cache lines: {"key": "<arch>/s<storage>/<nx>x<ny>", "rows": r, "nt": 0|1, "us": t}
-static bool tune_lookup(const char* path, const std::string& key, int& rows, int& nt) {
+// Cache lines: {"key": "<arch>/s<storage>/<nx>x<ny>", "rows": r, "nt": 0|1, "tile": w,
+// "us": t}; lines without "tile" (an earlier format) stand for 256-column tiles.
+static bool tune_lookup(const char* path, const std::string& key, int& rows, int& nt, int& tile_w) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char line[512];
     bool found = false;
     while (std::fgets(line, sizeof(line), f)) {
         char k[256];
-        int r = 0, n = 0;
+        int r = 0, n = 0, w = TILE_X;
         double us = 0;
-        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"rows\": %d, \"nt\": %d, \"us\": %lf", k, &r,
-                        &n, &us) == 4 &&
-            key == k && (r == 1 || r == 2 || r == 4) && (n == 0 || n == 1)) {
+        const bool with_tile =
+            std::sscanf(line, " {\"key\": \"%255[^\"]\", \"rows\": %d, \"nt\": %d, \"tile\": %d, \"us\": %lf",
+                        k, &r, &n, &w, &us) == 5;
+        if (!with_tile) {
+            w = TILE_X;
+            if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"rows\": %d, \"nt\": %d, \"us\": %lf", k,
+                            &r, &n, &us) != 4)
+                continue;
+        }
+        if (key == k && (r == 1 || r == 2 || r == 4) && (n == 0 || n == 1) &&
+            (w == TILE_X || w == TILE_WIDE)) {
             rows = r;
             nt = n;
+            tile_w = w;
             found = true;  // the last matching line wins
         }
     }
@@ -717,22 +740,24 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
     if (!s || trial_steps < 1) return fail(s, LBM_ERR_ARG, "bad argument");
     if (s->in_batch) return reject_member(s);
     const std::string key = tune_key(s);
-    int rows = 0, nt = 0;
+    int rows = 0, nt = 0, tile_w = TILE_X;
     double best = -1.0;
-    if (!(cache_path && tune_lookup(cache_path, key, rows, nt))) {
+    if (!(cache_path && tune_lookup(cache_path, key, rows, nt, tile_w))) {
         // candidates are timed from this simulation's current state, not from the uniform
         // start (whose exactly-zero offsets the memory system moves faster)
         HIP_TRY(s, hipStreamSynchronize(s->stream));
         const int cur = (int)(s->host_step & 1);
         const size_t outlet_bytes = 3 * (size_t)s->ny * (s->storage == LBM_FP64 ? 8 : 4);
         const int cand_rows[3] = {1, 2, 4};
-        for (int ci = 0; ci < 6; ++ci) {
+        const int cand_w[2] = {TILE_X, TILE_WIDE};
+        for (int ci = 0; ci < 12; ++ci) {
             lbm_opts o = s->opts;
             o.hip_stream = nullptr;
             o.pop_buffers[0] = o.pop_buffers[1] = nullptr;
             o.history_cap = 64;
-            o.rows_per_tile = cand_rows[ci / 2];
+            o.rows_per_tile = cand_rows[(ci / 2) % 3];
             o.store_mode = (ci & 1) ? LBM_STORE_NONTEMPORAL : LBM_STORE_PLAIN;
+            o.tile_width = cand_w[ci / 6];
             lbm_sim* t = nullptr;
             int rc = lbm_create(s->nx, s->ny, s->rates, s->eta, &o, &t);
             if (rc) return fail(s, rc, std::string("autotune: ") + lbm_last_error(nullptr));
@@ -760,24 +785,33 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
             const double us = 1e3 * ms / trial_steps;
             if (best < 0.0 || us < best) {
                 best = us;
-                rows = cand_rows[ci / 2];
+                rows = cand_rows[(ci / 2) % 3];
                 nt = ci & 1;
+                tile_w = cand_w[ci / 6];
             }
         }
         if (cache_path) {
             FILE* f = std::fopen(cache_path, "a");
             if (f) {
-                std::fprintf(f, "{\"key\": \"%s\", \"rows\": %d, \"nt\": %d, \"us\": %.3f}\n",
-                             key.c_str(), rows, nt, best);
+                std::fprintf(f, "{\"key\": \"%s\", \"rows\": %d, \"nt\": %d, \"tile\": %d, \"us\": %.3f}\n",
+                             key.c_str(), rows, nt, tile_w, best);
                 std::fclose(f);
             }
         }
     }
-    int rc = apply_launch_config(s, rows, nt != 0);
+    int rc = apply_launch_config(s, rows, nt != 0, tile_w);
     if (rc) return rc;
     if (rows_out) *rows_out = rows;
     if (nt_out) *nt_out = nt;
     if (us_out) *us_out = best;
+    return LBM_OK;
+}
+
+int lbm_launch_config(const lbm_sim* s, int* rows_out, int* nt_out, int* tile_width_out) {
+    if (!s) return LBM_ERR_ARG;
+    if (rows_out) *rows_out = s->rows;
+    if (nt_out) *nt_out = s->nt ? 1 : 0;
+    if (tile_width_out) *tile_width_out = s->desc.tile_w;
     return LBM_OK;
 }
 
@@ -841,9 +875,18 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     c += s->pop_bytes;
     HIP_TRY(s, hipMemcpy(s->outlet, c, ob, hipMemcpyHostToDevice));
     c += ob;
-    HIP_TRY(s, hipMemcpy(s->body_d, c, sizeof(BodyDev), hipMemcpyHostToDevice));
     BodyDev B;
     std::memcpy(&B, c, sizeof(B));
+    // the save flushed the state (fresh); its participation box is in the saver's tiles,
+    // which may differ from this simulation's
+    BodyState& st = B.st[s->host_step & 1];
+    BodyState& before = B.st[(s->host_step & 1) ^ 1];
+    if (st.fresh && B.active) {
+        body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, B, st.q[0], st.q[1], st.boxM);
+        body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, B, before.q[0], before.q[1], before.boxM);
+        for (int k = 0; k < 4; ++k) st.part_box[k] = before.boxM[k];
+    }
+    HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(BodyDev), hipMemcpyHostToDevice));
     s->has_body = B.active != 0;
     s->row_shift = dispatch_row_shift(B.st[s->host_step & 1].boxM, s->desc.tiles_y);
     if (!s->has_body) s->rec_end = s->drained = std::max(s->drained, s->host_step);
@@ -870,6 +913,7 @@ struct lbm_batch {
     int order = LBM_ORDER_LARGEST_FIRST;
     int rows = 1;
     bool nt = false;
+    int tile_w = TILE_X;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int64_t host_step = 0;
@@ -956,7 +1000,8 @@ static int batch_launch(lbm_batch* b) {
     const int p = (int)(b->host_step & 1);
     dispatch(b->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        Launch<S>::step_batch(b->descs_d, b->sched_d, b->nsched, b->rows, b->nt, p, b->stream);
+        Launch<S>::step_batch(b->descs_d, b->sched_d, b->nsched, b->rows, b->nt, b->tile_w, p,
+                              b->stream);
         return 0;
     });
     BHIP_TRY(b, hipGetLastError());
@@ -1006,6 +1051,8 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
         return g_batch_create_error = "unknown storage", LBM_ERR_ARG;
     if (bo.rows_per_tile != 0 && bo.rows_per_tile != 1 && bo.rows_per_tile != 2 && bo.rows_per_tile != 4)
         return g_batch_create_error = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
+    if (bo.tile_width != 0 && bo.tile_width != TILE_X && bo.tile_width != TILE_WIDE)
+        return g_batch_create_error = "tile_width must be 0, 256 or 512", LBM_ERR_ARG;
     lbm_batch* b = new lbm_batch();
     b->n = n;
     b->storage = bo.storage;
@@ -1038,6 +1085,7 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
         o.pop_buffers[0] = o.pop_buffers[1] = nullptr;
         o.rows_per_tile = bo.rows_per_tile;
         o.store_mode = bo.store_mode;
+        o.tile_width = bo.tile_width;
         b->in_opts[i] = o;
         if (descs[i].body) {
             b->in_body[i] = *descs[i].body;
@@ -1066,8 +1114,9 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
     b->rows = bo.rows_per_tile ? bo.rows_per_tile : 1;
     b->nt = bo.store_mode == LBM_STORE_NONTEMPORAL ||
             (bo.store_mode == LBM_STORE_AUTO && 2 * bytes > (size_t(1) << 30));
+    b->tile_w = bo.tile_width ? bo.tile_width : TILE_X;
     for (lbm_sim* s : b->sims) {
-        int rc = apply_launch_config(s, b->rows, b->nt);
+        int rc = apply_launch_config(s, b->rows, b->nt, b->tile_w);
         if (rc) return b->err = s->err, bail(rc);
     }
     hipError_t e = hipMalloc((void**)&b->descs_d, (size_t)n * sizeof(SimDesc));
@@ -1165,25 +1214,28 @@ int lbm_batch_sync(lbm_batch* b) {
     return worst;
 }
 
-static int batch_apply(lbm_batch* b, int rows, bool nt, int order) {
+static int batch_apply(lbm_batch* b, int rows, bool nt, int order, int tile_w) {
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     for (lbm_sim* s : b->sims) {
-        int rc = apply_launch_config(s, rows, nt);
+        int rc = apply_launch_config(s, rows, nt, tile_w);
         if (rc) return bfail(b, rc, s->err);
     }
     b->rows = rows;
     b->nt = nt;
     b->order = order;
+    b->tile_w = tile_w;
     return batch_upload(b);
 }
 
 // Times trial_steps steps of a scratch copy of the batch for each candidate.
-static int batch_time(lbm_batch* b, int rows, bool nt, int order, int trial_steps, double& us) {
+static int batch_time(lbm_batch* b, int rows, bool nt, int order, int tile_w, int trial_steps,
+                      double& us) {
     lbm_batch_opts bo = b->bopts;
     bo.hip_stream = nullptr;
     bo.rows_per_tile = rows;
     bo.store_mode = nt ? LBM_STORE_NONTEMPORAL : LBM_STORE_PLAIN;
     bo.order = order;
+    bo.tile_width = tile_w;
     std::vector<lbm_batch_desc> ds = b->in;
     for (int i = 0; i < b->n; ++i) {
         b->in_opts[i].history_cap = 64;
@@ -1221,28 +1273,31 @@ static int batch_time(lbm_batch* b, int rows, bool nt, int order, int trial_step
 int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* rows_out, int* nt_out, int* order_out,
                        double* us_out) {
     if (!b || trial_steps < 1) return bfail(b, LBM_ERR_ARG, "bad argument");
-    int best_rows = 1, best_order = LBM_ORDER_LARGEST_FIRST;
+    int best_rows = 1, best_order = LBM_ORDER_LARGEST_FIRST, best_w = TILE_X;
     bool best_nt = false;
     double best = -1.0, us = 0.0;
     const int cand_rows[3] = {1, 2, 4};
-    for (int ci = 0; ci < 6; ++ci) {
-        int rc = batch_time(b, cand_rows[ci / 2], ci & 1, LBM_ORDER_LARGEST_FIRST, trial_steps, us);
+    const int cand_w[2] = {TILE_X, TILE_WIDE};
+    for (int ci = 0; ci < 12; ++ci) {
+        const int rows = cand_rows[(ci / 2) % 3], w = cand_w[ci / 6];
+        int rc = batch_time(b, rows, ci & 1, LBM_ORDER_LARGEST_FIRST, w, trial_steps, us);
         if (rc) return rc;
         if (best < 0 || us < best) {
             best = us;
-            best_rows = cand_rows[ci / 2];
+            best_rows = rows;
             best_nt = ci & 1;
+            best_w = w;
         }
     }
     for (int order : {LBM_ORDER_GIVEN, LBM_ORDER_INTERLEAVED}) {
-        int rc = batch_time(b, best_rows, best_nt, order, trial_steps, us);
+        int rc = batch_time(b, best_rows, best_nt, order, best_w, trial_steps, us);
         if (rc) return rc;
         if (us < best) {
             best = us;
             best_order = order;
         }
     }
-    int rc = batch_apply(b, best_rows, best_nt, best_order);
+    int rc = batch_apply(b, best_rows, best_nt, best_order, best_w);
     if (rc) return rc;
     if (rows_out) *rows_out = best_rows;
     if (nt_out) *nt_out = best_nt;
@@ -1257,7 +1312,7 @@ int lbm_batch_configure(lbm_batch* b, int rows, int store_mode, int order) {
     if (store_mode != LBM_STORE_PLAIN && store_mode != LBM_STORE_NONTEMPORAL)
         return bfail(b, LBM_ERR_ARG, "store mode must be PLAIN or NONTEMPORAL");
     if (order < LBM_ORDER_GIVEN || order > LBM_ORDER_INTERLEAVED) return bfail(b, LBM_ERR_ARG, "unknown order");
-    return batch_apply(b, rows, store_mode == LBM_STORE_NONTEMPORAL, order);
+    return batch_apply(b, rows, store_mode == LBM_STORE_NONTEMPORAL, order, b->tile_w);
 }
 
 }  // extern "C"

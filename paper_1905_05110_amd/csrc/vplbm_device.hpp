@@ -18,7 +18,11 @@
 namespace vplbm {
 
 constexpr int NQ = 9;
-constexpr int TILE_X = 256;  // columns of a tile: one per lane of a 256-thread workgroup
+// A tile is TW columns (one per lane of a TW-thread workgroup) x ROWS rows; the step
+// kernel is built for TW = TILE_X and TILE_WIDE, chosen per launch.  TILE_X is also the
+// width of the adjoint's tiles and the workgroup size of the body-state sums.
+constexpr int TILE_X = 256;
+constexpr int TILE_WIDE = 512;
 constexpr int NWAVE = TILE_X / 64;
 // per-step FP64 sums: penalization force (2) and torque (1); momentum inside the body
 // after collision (2 + 1 angular) and before it (2 + 1); momentum-exchange force (2)
@@ -123,7 +127,8 @@ struct SimDesc {
     Record* hist;        // ring of per-step records
     int* flag;           // set to 1 when an unstable node is met
     long long ps;        // plane stride (elements)
-    int nx, ny, pitch, rows, tiles_x, tiles_y, hist_cap, pad;
+    int nx, ny, pitch, rows, tiles_x, tiles_y, hist_cap;
+    int tile_w;          // columns per tile of the step kernel: TILE_X or TILE_WIDE
     int bc[4];
     // x-edge rule (west, east) for the three directions whose source lies outside (1, 5, 8
     // at the west side, 3, 6, 7 at the east): source (i + dx, j + dy) and its plane
@@ -540,8 +545,9 @@ __device__ __forceinline__ DiscParams disc_params(const BodyDev* B) {
 // when the body is set) and stored per parity in BodyDev::box.
 // margin: nodes added around the support (1 for the exact box, 3 for participation).
 constexpr double BOX_MARGIN = 3.0;
-__host__ __device__ inline void body_tiles(int nx, int ny, int rows, const BodyDev& B, double X,
-                                           double Y, int box[4], double margin = BOX_MARGIN) {
+__host__ __device__ inline void body_tiles(int nx, int ny, int rows, int tile_w, const BodyDev& B,
+                                           double X, double Y, int box[4],
+                                           double margin = BOX_MARGIN) {
     box[0] = box[1] = box[2] = box[3] = 0;
     if (!B.active) return;
     const double xl = fmax(floor(X - B.reach) - margin, 0.0);
@@ -549,8 +555,8 @@ __host__ __device__ inline void body_tiles(int nx, int ny, int rows, const BodyD
     const double yl = fmax(floor(Y - B.reach) - margin, 0.0);
     const double yh = fmin(ceil(Y + B.reach) + margin, (double)(ny - 1));
     if (!(xl <= xh) || !(yl <= yh)) return;
-    box[0] = (int)xl / TILE_X;
-    box[1] = (int)xh / TILE_X;
+    box[0] = (int)xl / tile_w;
+    box[1] = (int)xh / tile_w;
     box[2] = (int)yl / rows;
     box[3] = (int)yh / rows;
 }
@@ -838,16 +844,16 @@ __device__ __forceinline__ void pull_wave_edge(const SimDesc& d,
 }
 
 // ---- one tile of one step ------------------------------------------------------------
-// A tile is TILE_X columns x ROWS rows; each lane walks down its column, issuing the
+// A tile is TW columns x ROWS rows; each lane walks down its column, issuing the
 // next row's nine loads before colliding the current row.  Nodes are pulled,
 // penalized, collided and stored.  PART tiles (those meeting the body) also rasterise
 // chi and u_s and accumulate force, torque and internal momentum in FP64.
 // First row of a tile: the pulled offsets of node (i, j0), interior or edge.
-template <class S>
+template <class S, int TW>
 __device__ __forceinline__ void pull_first(const SimDesc& d,
                                            const TileScalars<typename Codec<S>::T>& ts, int tx,
                                            int ty, int rows, typename Codec<S>::T g[NQ]) {
-    const int i = tx * TILE_X + (int)threadIdx.x;
+    const int i = tx * TW + (int)threadIdx.x;
     const int j0 = ty * rows;
     // a wave with any edge node takes the boundary-rule pull for all its lanes (it
     // handles interior nodes too): one path and one round of loads per wave
@@ -863,7 +869,7 @@ __device__ __forceinline__ void pull_first(const SimDesc& d,
     }
 }
 
-template <class S, int ROWS, bool NT, bool PART>
+template <class S, int ROWS, bool NT, bool PART, int TW>
 __device__ __forceinline__ void step_rows(const SimDesc& d,
                                           const TileScalars<typename Codec<S>::T>& c, int tx,
                                           int ty, double acc[NRED], const double* pose,
@@ -871,7 +877,7 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
     using T = typename Codec<S>::T;
     const char* fin = c.fin;
     char* fout = c.fout;
-    const int i = tx * TILE_X + (int)threadIdx.x;
+    const int i = tx * TW + (int)threadIdx.x;
     const int j0 = ty * ROWS;
     const int nx = c.nx, ny = c.ny;
     const bool col_ok = i < nx;
@@ -960,11 +966,11 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
 // populations it has just written along their links (the values that stream).  The
 // directions are walked one at a time, apart from the collision, so that this adds no
 // registers to it.
-template <class S, int ROWS>
+template <class S, int ROWS, int TW>
 __device__ __forceinline__ void mem_pass(const SimDesc& d, int tx, int ty, int p,
                                          const double* pose, double m[3]) {
     const BodyDev& B = *d.body;
-    const int i = tx * TILE_X + (int)threadIdx.x;
+    const int i = tx * TW + (int)threadIdx.x;
     m[0] = m[1] = m[2] = 0.0;
     if (!B.active || !B.mem || i >= d.nx) return;
     // uniform over the workgroup: kept in scalar registers
@@ -1011,20 +1017,23 @@ __device__ __forceinline__ void mem_pass(const SimDesc& d, int tx, int ty, int p
     m[2] = mt;
 }
 
-// Fixed-order FP64 sum of a step's partial slots by one workgroup of TILE_X threads
-// into tot (LDS); every caller obtains bitwise the same totals.
+// Fixed-order FP64 sum of a step's partial slots into tot (LDS) by the first TILE_X
+// threads of a workgroup (of TILE_X or more threads; the others only meet the
+// barriers): every caller, whatever its tile width, obtains bitwise the same totals.
 __device__ __forceinline__ void sum_slots(const double* __restrict__ slots, int nb,
-                                          double red[NWAVE][NRED], double* tot) {
+                                          double red[][NRED], double* tot) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double t[NRED];
+    if (threadIdx.x < TILE_X) {  // uniform over each wave
+        double t[NRED];
 #pragma unroll
-    for (int k = 0; k < NRED; ++k) t[k] = 0.0;
-    for (int s = threadIdx.x; s < nb; s += TILE_X)
-        for (int k = 0; k < NRED; ++k) t[k] += slots[(long long)s * NRED + k];
+        for (int k = 0; k < NRED; ++k) t[k] = 0.0;
+        for (int s = threadIdx.x; s < nb; s += TILE_X)
+            for (int k = 0; k < NRED; ++k) t[k] += slots[(long long)s * NRED + k];
 #pragma unroll
-    for (int k = 0; k < NRED; ++k) {
-        const double v = wave_sum(t[k]);
-        if (lane == 0) red[wave][k] = v;
+        for (int k = 0; k < NRED; ++k) {
+            const double v = wave_sum(t[k]);
+            if (lane == 0) red[wave][k] = v;
+        }
     }
     __syncthreads();
     if (threadIdx.x < NRED) {
@@ -1047,7 +1056,7 @@ __device__ __forceinline__ int box_count(const int b[4]) { return (b[1] - b[0] +
 // (25)-(27)); on the first step after the body is set the pre-collision momentum stands
 // in for the previous P_in.  The result is left in bs (LDS) for all threads; the work
 // runs in parallel lanes so that it needs no stack and few registers.
-__device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[NWAVE][NRED],
+__device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[][NRED],
                                             BodyStep& bs) {
     const BodyDev& B = *d.body;
     const BodyState& prev = B.st[p ^ 1];
@@ -1123,7 +1132,7 @@ __device__ __forceinline__ void store_state(BodyState& cur, const BodyState& pre
     cur.pin_valid = 1;
     for (int k = 0; k < 4; ++k) {
         cur.boxM[k] = bs.boxM[k];
-        cur.part_box[k] = fresh ? bs.boxM[k] : prev.boxM[k];
+        cur.part_box[k] = prev.boxM[k];
     }
     cur.fresh = fresh;
 }
@@ -1136,15 +1145,15 @@ __device__ __forceinline__ void store_state(BodyState& cur, const BodyState& pre
 // The caller maps workgroups to tiles (the host rotates the rows so that those of the
 // body are dispatched early, a sixteenth of the grid in: their longer work then overlaps
 // the rest of the grid instead of extending the end of the kernel).
-template <class S, int ROWS, bool NT>
+template <class S, int ROWS, bool NT, int TW>
 __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p) {
     using T = typename Codec<S>::T;
-    __shared__ double red[NWAVE][NRED];
+    __shared__ double red[TW / 64][NRED];
     __shared__ double pose_set[6];
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
-    // The step's scalars, then the participation box (both parities read, then selected:
-    // no dependent load), then the first row's populations.
+    // The step's scalars, then the participation box and whether this step's state is
+    // final already, then the first row's populations.
     const TileScalars<T> ts = tile_scalars<S>(d, p);
     // The box is read with vector-memory (buffer) loads whose values stay in vector
     // registers until the pull has been issued: a uniform load result is otherwise
@@ -1162,23 +1171,23 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     const int sp = vz + p * (int)sizeof(BodyState), sq = vz + (p ^ 1) * (int)sizeof(BodyState);
     constexpr int o_fresh = (int)offsetof(BodyState, fresh), o_box = (int)offsetof(BodyState, boxM);
     const int fresh_v = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_fresh, 0, 0);
-    int box_p[4], box_q[4];
+    int box_q[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        box_p[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sp + o_box + 4 * k, 0, 0);
-        box_q[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sq + o_box + 4 * k, 0, 0);
-    }
+    for (int k = 0; k < 4; ++k) box_q[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sq + o_box + 4 * k, 0, 0);
     T g[NQ];
-    pull_first<S>(d, ts, tx, ty, ROWS, g);
+    pull_first<S, TW>(d, ts, tx, ty, ROWS, g);
     const int fresh = __builtin_amdgcn_readfirstlane(fresh_v);
+    // the tiles that take part: the box of the previous step's pose (with a margin that
+    // covers this step's), whether this step's state is derived or was made final by a
+    // flush, so that flushes do not change which slots the sums are made of
     int pb[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pb[k] = __builtin_amdgcn_readfirstlane(fresh ? box_p[k] : box_q[k]);
+    for (int k = 0; k < 4; ++k) pb[k] = __builtin_amdgcn_readfirstlane(box_q[k]);
     const int bx0 = pb[0], bx1 = pb[1], by0 = pb[2], by1 = pb[3];
     const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
     double acc[NRED];
     if (!part) {
-        step_rows<S, ROWS, NT, false>(d, ts, tx, ty, acc, nullptr, g);
+        step_rows<S, ROWS, NT, false, TW>(d, ts, tx, ty, acc, nullptr, g);
         return;  // uniform over the workgroup
     }
     const bool writer = tx == bx0 && ty == by0;
@@ -1198,7 +1207,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     }
 #pragma unroll
     for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
-    step_rows<S, ROWS, NT, true>(d, ts, tx, ty, acc, pose, g);
+    step_rows<S, ROWS, NT, true, TW>(d, ts, tx, ty, acc, pose, g);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -1209,7 +1218,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     // the momentum-exchange pass runs once the other sums have left the registers
     if (B.mem) {  // uniform
         double m[3];
-        mem_pass<S, ROWS>(d, tx, ty, p, pose, m);
+        mem_pass<S, ROWS, TW>(d, tx, ty, p, pose, m);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double s = wave_sum(m[k]);
@@ -1222,7 +1231,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     if (threadIdx.x < NRED) {
         const int k = threadIdx.x;
         double s = red[0][k];
-        for (int w = 1; w < NWAVE; ++w) s += red[w][k];
+        for (int w = 1; w < TW / 64; ++w) s += red[w][k];
         const int slot = (ty - by0) * (bx1 - bx0 + 1) + (tx - bx0);
         d.partials[(long long)p * d.part_stride + (long long)slot * NRED + k] = s;
     }
@@ -1231,9 +1240,9 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
         if (!fresh) {
             const BodyState& prev = B.st[p ^ 1];
             int exact[4];
-            body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], exact, 1.0);
+            body_tiles(d.nx, d.ny, d.rows, d.tile_w, B, bs.qv[0], bs.qv[1], exact, 1.0);
             if (!box_inside(exact, pb)) raise_flag(d.flag, 2);  // moved >= 2 nodes in a step
-            body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], bs.boxM);
+            body_tiles(d.nx, d.ny, d.rows, d.tile_w, B, bs.qv[0], bs.qv[1], bs.boxM);
             write_record(d, prev, bs);
             store_state(B.st[p], prev, bs, 0);
         }
@@ -1253,9 +1262,9 @@ __device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
     if (threadIdx.x == 0) {
         const BodyState& prev = B.st[p ^ 1];
         int exact[4];
-        body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], exact, 1.0);
+        body_tiles(d.nx, d.ny, d.rows, d.tile_w, B, bs.qv[0], bs.qv[1], exact, 1.0);
         if (!box_inside(exact, prev.boxM)) raise_flag(d.flag, 2);
-        body_tiles(d.nx, d.ny, d.rows, B, bs.qv[0], bs.qv[1], bs.boxM);
+        body_tiles(d.nx, d.ny, d.rows, d.tile_w, B, bs.qv[0], bs.qv[1], bs.boxM);
         write_record(d, prev, bs);
         store_state(B.st[p], prev, bs, 1);
     }

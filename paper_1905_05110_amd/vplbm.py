@@ -26,7 +26,8 @@ ORDER = {"given": 0, "largest_first": 1, "interleaved": 2}
 EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
            "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
            "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
-           "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_save", "lbm_load",
+           "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_launch_config",
+           "lbm_save", "lbm_load",
            "lbm_destroy", "lbm_last_error",
            "lbm_default_batch_opts", "lbm_batch_create", "lbm_batch_step",
            "lbm_batch_set_graph_steps", "lbm_batch_sync", "lbm_batch_sim", "lbm_batch_size",
@@ -55,7 +56,7 @@ class Opts(C.Structure):
                 ("storage", C.c_int), ("fp16_scale_log2", C.c_int), ("history_cap", C.c_int),
                 ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
                 ("hip_stream", C.c_void_p),
-                ("pop_buffers", C.c_void_p * 2), ("collision", C.c_int)]
+                ("pop_buffers", C.c_void_p * 2), ("collision", C.c_int), ("tile_width", C.c_int)]
 
 
 class Body(C.Structure):
@@ -76,7 +77,7 @@ class BatchDesc(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("storage", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
-                ("order", C.c_int), ("hip_stream", C.c_void_p)]
+                ("order", C.c_int), ("hip_stream", C.c_void_p), ("tile_width", C.c_int)]
 
 
 class AdjointOpts(C.Structure):
@@ -122,6 +123,7 @@ def load_library(path=LIB_PATH):
     L.lbm_step_timed.argtypes = [P, C.c_int64, _DP, _DP]
     L.lbm_autotune.argtypes = [P, C.c_int, C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_double)]
+    L.lbm_launch_config.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_save.argtypes = [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbm_load.argtypes = [P, C.c_void_p, C.c_size_t]
     L.lbm_destroy.argtypes = [P]
@@ -188,6 +190,7 @@ def make_opts(spec, stream=None, buffers=None, history_cap=65536):
     o.rows_per_tile = int(spec.get("rows_per_tile", 0))
     o.store_mode = {"auto": 0, "plain": 1, "nontemporal": 2}[spec.get("store_mode", "auto")]
     o.collision = {"mrt": 0, "bgk": 1}[spec.get("collision", "mrt")]
+    o.tile_width = int(spec.get("tile_width", 0))
     o.hip_stream = stream
     if buffers is not None:
         o.pop_buffers[0], o.pop_buffers[1] = buffers
@@ -326,12 +329,19 @@ class Sim:
         return k.value, r.value
 
     def autotune(self, trial_steps=20, cache=None):
-        """Pick rows per tile and store mode by timing; returns (rows, nt, us/step)."""
+        """Pick rows per tile, store mode and columns per tile by timing; returns (rows, nt,
+        us/step); launch_config() also gives the columns per tile."""
         r, n, us = C.c_int(), C.c_int(), C.c_double()
         path = cache.encode() if cache else None
         self._check(self.L.lbm_autotune(self.h, int(trial_steps), path, C.byref(r), C.byref(n),
                                         C.byref(us)))
         return r.value, n.value, us.value
+
+    def launch_config(self):
+        """The launch configuration in use: (rows per tile, nt flag, columns per tile)."""
+        r, n, w = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.L.lbm_launch_config(self.h, C.byref(r), C.byref(n), C.byref(w)))
+        return r.value, n.value, w.value
 
     def save(self):
         size = C.c_size_t()
@@ -373,7 +383,7 @@ class Batch:
     """
 
     def __init__(self, members, storage="fp32", order="largest_first", rows=0, store="auto",
-                 history_cap=65536, graph_steps=0, stream=None):
+                 history_cap=65536, graph_steps=0, stream=None, tile_width=0):
         L = load_library()
         self.L = L
         self.h = None
@@ -397,6 +407,7 @@ class Batch:
         bo.rows_per_tile = int(rows)
         bo.store_mode = STORE[store] if isinstance(store, str) else int(store)
         bo.hip_stream = stream
+        bo.tile_width = int(tile_width)
         h = C.c_void_p()
         rc = L.lbm_batch_create(n, descs, C.byref(bo), C.byref(h))
         if rc != LBM_OK:
@@ -433,7 +444,8 @@ class Batch:
             ORDER[order] if isinstance(order, str) else int(order)))
 
     def autotune(self, trial_steps=20):
-        """Pick rows, store mode and order by timing; returns (rows, nt, order, us/step)."""
+        """Pick rows, store mode, columns per tile and order by timing; returns (rows, nt,
+        order, us/step); a member's launch_config() gives the columns per tile."""
         r, n, o, us = C.c_int(), C.c_int(), C.c_int(), C.c_double()
         self._check(self.L.lbm_batch_autotune(self.h, int(trial_steps), C.byref(r), C.byref(n),
                                               C.byref(o), C.byref(us)))

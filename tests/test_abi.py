@@ -58,6 +58,8 @@ def _create(lib, nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3, **kw):
     (dict(bc=("outflow", "wall", "wall", "wall")), "OUTFLOW"),
     (dict(bc=("wall", "wall", "outflow", "wall")), "OUTFLOW"),
     (dict(storage=7), "storage"),
+    (dict(tile_width=384), "tile_width"),
+    (dict(tile_width=128), "tile_width"),
     (dict(storage="fp16", fp16_scale_log2=20), "fp16_scale"),
 ])
 def test_invalid_arguments_are_rejected(lib, kw, frag):
@@ -98,6 +100,7 @@ def _batch_desc(nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3):
     ("store_mode", 5, "store mode"),
     ("storage", 9, "storage"),
     ("rows_per_tile", 3, "rows_per_tile"),
+    ("tile_width", 384, "tile_width"),
 ])
 def test_invalid_batch_options_are_rejected(lib, field, value, frag):
     descs = (vplbm.BatchDesc * 2)(_batch_desc(), _batch_desc(12, 9))
@@ -123,7 +126,7 @@ def test_batch_null_arguments_are_rejected(lib):
 
 
 def test_batch_struct_layout(lib):
-    assert C.sizeof(vplbm.BatchOpts) == 4 * 4 + 8
+    assert C.sizeof(vplbm.BatchOpts) == 4 * 4 + 8 + 4 + 4  # tile_width, then padding
     assert C.sizeof(vplbm.BatchDesc) == 4 * 2 + 8 * 4 + 8 + 8 + 8
 
 

@@ -58,18 +58,22 @@ def mixed_members(storage):
     return out
 
 
-@pytest.mark.parametrize("storage,rows,store", [("fp64", 1, "plain"), ("fp32", 2, "plain"),
-                                                ("fp16", 4, "nontemporal"),
-                                                ("bf16", 2, "nontemporal")])
-def test_members_are_bitwise_equal_to_standalone_runs(gpu, storage, rows, store):
-    _flush("batch vs standalone %s rows %d %s" % (storage, rows, store))
+@pytest.mark.parametrize("storage,rows,store,tile", [("fp64", 1, "plain", 256),
+                                                     ("fp32", 2, "plain", 256),
+                                                     ("fp16", 4, "nontemporal", 256),
+                                                     ("bf16", 2, "nontemporal", 256),
+                                                     ("fp32", 1, "plain", 512),
+                                                     ("fp16", 2, "nontemporal", 512)])
+def test_members_are_bitwise_equal_to_standalone_runs(gpu, storage, rows, store, tile):
+    _flush("batch vs standalone %s rows %d %s tile %d" % (storage, rows, store, tile))
     members = mixed_members(storage)
-    batch = gpu.Batch(members, storage=storage, rows=rows, store=store, graph_steps=8)
+    batch = gpu.Batch(members, storage=storage, rows=rows, store=store, graph_steps=8,
+                      tile_width=tile)
     batch.step(3)
     batch.step(30)
     batch.sync()
     for i, (spec, body) in enumerate(members):
-        s = gpu.Sim(dict(spec, rows_per_tile=rows, store_mode=store), body)
+        s = gpu.Sim(dict(spec, rows_per_tile=rows, store_mode=store, tile_width=tile), body)
         s.step(33)
         s.sync()
         m = batch.sims[i]
@@ -157,6 +161,9 @@ def test_batch_autotune_and_sweep(gpu):
     batch = gpu.Batch(members, storage="fp32", graph_steps=16, history_cap=256)
     rows, nt, order, us = batch.autotune(trial_steps=8)
     assert rows in (1, 2, 4) and nt in (0, 1) and order in (0, 1, 2) and us > 0
+    cfg = batch.sims[0].launch_config()
+    assert cfg[:2] == (rows, nt) and cfg[2] in (256, 512)
+    assert all(m.launch_config() == cfg for m in batch.sims)
     batch.step(64)
     batch.sync()
     q, v = batch.sims[17].body_state()

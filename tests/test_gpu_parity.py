@@ -173,16 +173,17 @@ def test_tiny_grids_step_by_step_reduced(gpu, storage, bcname, bodykind):
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16", "fp32"])
 @pytest.mark.parametrize("bcname", ["channel", "periodic", "wallbox"])
-@pytest.mark.parametrize("rows", [1, 2])
-def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows):
-    """601 x 40 (three 256-column tiles, the last ragged and of odd width), free body
-    across a tile border: one step at a time from the stored state, against the oracle.
-    16-bit storage moves node pairs as 32-bit words with lane shifts in interior waves."""
+@pytest.mark.parametrize("rows,tile", [(1, 256), (2, 256), (1, 512), (2, 512)])
+def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows, tile):
+    """601 x 40 (three 256-column tiles or two 512-column ones, the last ragged and of odd
+    width), free body across the first 256-column border: one step at a time from the
+    stored state, against the oracle."""
     from oracle import oracle as orc
     nx, ny = 601, 40
     spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04, storage=storage,
                    g=(2e-5, -1e-5) if bcname == "periodic" else (0.0, 0.0))
     spec["rows_per_tile"] = rows
+    spec["tile_width"] = tile
     b = W.fixed_disc(14.0, 255.6, 19.3)
     b.update(mode="free", free_mask=7, mass=300.0, inertia=2000.0, k=(0.01, 0.01, 0.0),
              q0=(255.6, 19.3, 0.0))
@@ -201,32 +202,36 @@ def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows):
 
 
 @pytest.mark.parametrize("bcname", list(BCS))
-@pytest.mark.parametrize("nx,ny,rows", [(130, 12, 1), (130, 12, 2), (600, 9, 2)])
-def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows):
+@pytest.mark.parametrize("nx,ny,rows,tile", [(130, 12, 1, 256), (130, 12, 2, 256), (600, 9, 2, 256),
+                                             (600, 9, 1, 512), (1100, 7, 2, 512)])
+def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows, tile):
     """Grids wider than a wave: the waves holding the west or the east node of an
     interior row take the x-edge pull (the east node at 129 sits in a partly filled
     wave), the first and last rows the general one; every boundary set, rows per tile 1
     and 2 (the second row's pull comes after the first row's stores), a body near the
     west edge."""
-    _flush("x-edge %s %dx%d rows %d" % (bcname, nx, ny, rows))
+    _flush("x-edge %s %dx%d rows %d tile %d" % (bcname, nx, ny, rows, tile))
     spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04,
                    g=(2e-5, -1e-5) if bcname in ("periodic", "pipe") else (0.0, 0.0))
     spec["rows_per_tile"] = rows
+    spec["tile_width"] = tile
     b = W.fixed_disc(5.0, 4.3, ny / 2.0 - 0.3)
     b.update(vx=0.002, omega=0.001, force_model="vp+mem")
     run_pair(gpu, spec, b, steps=6, seed=7)
 
 
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
-def test_several_tiles_and_ragged_tail_fp64(gpu, bcname):
-    """nx = 600 spans three 256-wide tiles, the last one ragged; the body straddles
-    a tile border."""
+@pytest.mark.parametrize("tile,xb", [(256, 256.3), (512, 511.7)])
+def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb):
+    """nx = 600 spans three 256-wide tiles or two 512-wide ones, the last one ragged;
+    the body straddles a tile border."""
     nx, ny = 600, 24
-    _flush("ragged %s" % bcname)
+    _flush("ragged %s tile %d" % (bcname, tile))
     spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04)
-    b = W.fixed_disc(14.0, 256.3, 11.6)
+    spec["tile_width"] = tile
+    b = W.fixed_disc(14.0, xb, 11.6)
     b.update(mode="free", free_mask=7, mass=300.0, inertia=2000.0, k=(0.01, 0.01, 0.0),
-             q0=(256.3, 11.6, 0.0))
+             q0=(xb, 11.6, 0.0))
     run_pair(gpu, spec, b, steps=8, seed=99, check_every=2)
 
 
@@ -316,6 +321,29 @@ def test_same_configuration_is_deterministic(gpu):
     assert np.array_equal(runs[0][1]["fvp"], runs[1][1]["fvp"])
 
 
+@pytest.mark.parametrize("tile", [256, 512])
+def test_flushes_do_not_change_results(gpu, tile):
+    """A synchronising call makes the pending body state final with a one-workgroup
+    kernel of 256 threads; the step's own tiles (256 or 512 threads) derive the same
+    state: a run synchronised after every step is bitwise the run that never is."""
+    wl = W.imposed_oscillation(storage="fp32", nx=600, ny=90, D=24.0)
+    wl["body"].update(mode="free", free_mask=7, mass=400.0, inertia=4000.0, k=(0.01, 0.01, 0.0))
+    spec = dict(wl["spec"], tile_width=tile)
+    a = gpu.Sim(spec, wl["body"])
+    b = gpu.Sim(spec, wl["body"])
+    for _ in range(25):
+        a.step(1)
+        a.sync()
+    b.step(25)
+    b.sync()
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    ra, rb = a.forces(), b.forces()
+    for key in ("fvp", "pin", "fh", "q", "v"):
+        assert np.array_equal(ra[key], rb[key]), key
+    a.close()
+    b.close()
+
+
 def test_graph_replay_is_bitwise_equal_to_eager(gpu):
     wl = W.imposed_oscillation(storage="fp32")
     a = gpu.Sim(wl["spec"], wl["body"])
@@ -345,6 +373,26 @@ def test_save_and_load_resume_bitwise(gpu):
     assert np.array_equal(b.get_populations(), ref)
     rb = b.forces()
     assert np.array_equal(rb["fvp"][-30:], rref["fvp"])
+    a.close()
+    b.close()
+
+
+def test_save_and_load_across_tile_widths(gpu):
+    """A state saved by a simulation with 256-column tiles resumes in one with 512-column
+    tiles (the body's participation box is re-expressed in the loader's tiles): the
+    continuation agrees with the saver's own to rounding."""
+    wl = W.imposed_oscillation(storage="fp32", nx=600, ny=90, D=24.0)
+    wl["body"].update(x=300.4, q0=(300.4, 45.0, 0.0), imp_y0=45.0)
+    a = gpu.Sim(dict(wl["spec"], tile_width=256), wl["body"])
+    a.step(40)
+    blob = a.save()
+    a.step(30)
+    b = gpu.Sim(dict(wl["spec"], tile_width=512), wl["body"])
+    b.load(blob)
+    b.step(30)
+    assert rel(b.get_populations(), a.get_populations()) <= 1e-6
+    ra, rb = a.forces()[-30:], b.forces()[-30:]
+    assert rel(rb["fvp"], ra["fvp"]) <= 1e-4
     a.close()
     b.close()
 
@@ -403,23 +451,24 @@ def test_full_size_free_viv_first_steps(gpu, storage):
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
 def test_launch_configurations_agree(gpu, storage):
-    """Rows per tile and store instructions change the schedule, not the method: the
+    """Rows and columns per tile and store instructions change the schedule, not the method: the
     compiler may contract multiply-adds differently in each kernel instantiation, so
     populations agree to rounding (each configuration itself is deterministic)."""
     wl = W.imposed_oscillation(storage=storage, nx=600, ny=90, D=24.0)
     ref = None
-    for rows in (1, 2, 4):
-        for store in ("plain", "nontemporal"):
-            g = gpu.Sim(dict(wl["spec"], rows_per_tile=rows, store_mode=store), wl["body"])
-            g.step(30)
-            f, r = g.get_populations(), g.forces()
-            g.close()
-            if ref is None:
-                ref = (f, r)
-                continue
-            tol = {"fp64": 1e-14, "fp32": 1e-6, "fp16": 1e-4}[storage]
-            assert rel(f, ref[0]) <= tol, (rows, store)
-            assert rel(r["fvp"], ref[1]["fvp"]) <= 100 * tol
+    configs = [(r, s, t) for t in (256, 512) for r in (1, 2, 4) for s in ("plain", "nontemporal")]
+    for rows, store, tile in configs:
+        g = gpu.Sim(dict(wl["spec"], rows_per_tile=rows, store_mode=store, tile_width=tile),
+                    wl["body"])
+        g.step(30)
+        f, r = g.get_populations(), g.forces()
+        g.close()
+        if ref is None:
+            ref = (f, r)
+            continue
+        tol = {"fp64": 1e-14, "fp32": 1e-6, "fp16": 1e-4}[storage]
+        assert rel(f, ref[0]) <= tol, (rows, store, tile)
+        assert rel(r["fvp"], ref[1]["fvp"]) <= 100 * tol
 
 
 def test_autotune_applies_a_configuration(gpu, tmp_path):
@@ -428,9 +477,11 @@ def test_autotune_applies_a_configuration(gpu, tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     rows, nt, us = a.autotune(trial_steps=5, cache=cache)
     assert rows in (1, 2, 4) and nt in (0, 1) and us > 0
+    assert a.launch_config()[:2] == (rows, nt) and a.launch_config()[2] in (256, 512)
     b = gpu.Sim(wl["spec"], wl["body"])
     rows2, nt2, us2 = b.autotune(trial_steps=5, cache=cache)  # from the cache
     assert (rows2, nt2, us2) == (rows, nt, -1.0)
+    assert b.launch_config() == a.launch_config()
     a.step(20)
     b.step(20)
     assert np.array_equal(a.get_populations(), b.get_populations())
