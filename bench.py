@@ -339,8 +339,8 @@ def run_adjoint(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; it "
+              "measures one GPU's share of the work", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch_sweep":
         return run_batch(args)
