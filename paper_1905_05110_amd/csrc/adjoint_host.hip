@@ -67,15 +67,17 @@ struct lbm_adjoint {
     lbm_body body{};
     size_t tsz = 4, out_bytes = 0;
     AdjDesc ad{};
-    AdjDesc* ad_d = nullptr;
-    SimDesc* seg_descs_d = nullptr;
+    // Two segment stores: the backward sweep over segment m (reading one store) runs
+    // alongside the recomputation of segment m - 1 (writing the other) on a second stream.
+    AdjDesc* ad_d = nullptr;        // adjoint descriptors of store 0 and store 1 (two)
+    SimDesc* seg_descs_d = nullptr; // forward step descriptors: K for store 0, then K for 1
     char* def_pop = nullptr;  // the uniform initial state of lbm_create
     char* def_out = nullptr;
     char* init_pop = nullptr;  // initial state of the forward run
     char* init_out = nullptr;
     char* ckpt_pop = nullptr;
     char* ckpt_out = nullptr;
-    char* seg_pop = nullptr;
+    char* seg_pop = nullptr;  // store 0; store 1 follows it (2 (K + 1) buffers in all)
     char* seg_out = nullptr;
     void* abar[2] = {nullptr, nullptr};
     void* chibar = nullptr;
@@ -89,8 +91,10 @@ struct lbm_adjoint {
     bool fwd_done = false, bwd_done = false;
     double J = 0.0;
     std::vector<lbm_force_rec> recs;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipStream_t aux = nullptr;  // the recomputation's stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};  // one backward stage per parity of m
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     std::string err;
 };
 
@@ -215,8 +219,12 @@ void set_pose(lbm_adjoint* A) {
     ad.nbox[3] = std::min(A->ny - 1, (int)std::ceil(b.y + reach) + 1);
 }
 
+// The adjoint descriptors of the two segment stores (they differ in the store only).
 int upload_ad(lbm_adjoint* A) {
-    AHIP_TRY(A, hipMemcpy(A->ad_d, &A->ad, sizeof(AdjDesc), hipMemcpyHostToDevice));
+    AdjDesc two[2] = {A->ad, A->ad};
+    two[1].seg_pop = A->ad.seg_pop + (A->K + 1) * A->ad.seg_stride;
+    two[1].seg_out = A->ad.seg_out + (A->K + 1) * A->ad.out_stride;
+    AHIP_TRY(A, hipMemcpy(A->ad_d, two, sizeof(two), hipMemcpyHostToDevice));
     return LBM_OK;
 }
 
@@ -229,32 +237,75 @@ int zero_words(lbm_adjoint* A, void* p, size_t bytes) {
     return LBM_OK;
 }
 
-// One segment of the backward sweep, enqueued on the simulation's stream.
-int enqueue_segment(lbm_adjoint* A) {
+// Recomputation of the segment the device counter names, into segment store `store`:
+// checkpoint -> slot 0, K forward steps (slot i -> i + 1), then the counter moves to the
+// previous segment.  Enqueued on stream st.
+int enqueue_recompute(lbm_adjoint* A, int store, hipStream_t st) {
     lbm_sim* s = A->sim;
     const long long words = (long long)(s->pop_bytes / 4);
     const int blocks = (int)std::min<long long>(4096, (words + 255) / 256);
-    hipLaunchKernelGGL(k_adj_load_segment, dim3(blocks), dim3(256), 0, s->stream, A->ad_d);
+    hipLaunchKernelGGL(k_adj_load_segment, dim3(blocks), dim3(256), 0, st, A->ad_d + store);
     const dim3 fgrid(s->desc.tiles_x, s->desc.tiles_y);
-    const dim3 agrid(A->atx, A->ny);
+    const SimDesc* sd = A->seg_descs_d + (size_t)store * A->K;
     dispatch(A->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         for (int i = 0; i < A->K; ++i)
-            Launch<S>::step(A->seg_descs_d + i, fgrid, s->rows, s->nt, s->desc.tile_w, i & 1, s->stream,
-                            s->row_shift);
-        if constexpr (std::is_same_v<S, double> || std::is_same_v<S, float>)
-            for (int i = A->K - 1; i >= 0; --i) AdjLaunch<S>::step(s->desc_d, A->ad_d, agrid, i, s->stream);
+            Launch<S>::step(sd + i, fgrid, s->rows, s->nt, s->desc.tile_w, i & 1, st, s->row_shift);
         return 0;
     });
-    hipLaunchKernelGGL(k_adj_next_segment, dim3(1), dim3(64), 0, s->stream, A->ad_d);
+    hipLaunchKernelGGL(k_adj_next_segment, dim3(1), dim3(64), 0, st, A->ad_d);
     AHIP_TRY(A, hipGetLastError());
     return LBM_OK;
 }
 
+// Backward sweep over the segment held in store `store` (K adjoint steps, last first).
+int enqueue_sweep(lbm_adjoint* A, int store, hipStream_t st) {
+    lbm_sim* s = A->sim;
+    const dim3 agrid(A->atx, A->ny);
+    dispatch(A->storage, [&](auto* tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        if constexpr (std::is_same_v<S, double> || std::is_same_v<S, float>)
+            for (int i = A->K - 1; i >= 0; --i) AdjLaunch<S>::step(s->desc_d, A->ad_d + store, agrid, i, st);
+        return 0;
+    });
+    AHIP_TRY(A, hipGetLastError());
+    return LBM_OK;
+}
+
+// Stage m of the backward run (m = nseg - 1 .. 1): the sweep over segment m (store
+// m & 1) on the simulation's stream alongside the recomputation of segment m - 1 (the
+// other store) on the second stream; the stage ends when both have.
+int enqueue_stage(lbm_adjoint* A, int parity) {
+    hipStream_t st = A->sim->stream;
+    AHIP_TRY(A, hipEventRecord(A->ev_fork, st));
+    AHIP_TRY(A, hipStreamWaitEvent(A->aux, A->ev_fork, 0));
+    int rc = enqueue_recompute(A, parity ^ 1, A->aux);
+    if (rc) return rc;
+    rc = enqueue_sweep(A, parity, st);
+    if (rc) return rc;
+    AHIP_TRY(A, hipEventRecord(A->ev_join, A->aux));
+    AHIP_TRY(A, hipStreamWaitEvent(st, A->ev_join, 0));
+    return LBM_OK;
+}
+
+void drop_stage_graphs(lbm_adjoint* A) {
+    for (int q = 0; q < 2; ++q) {
+        if (A->gexec[q]) (void)hipGraphExecDestroy(A->gexec[q]);
+        if (A->graph[q]) (void)hipGraphDestroy(A->graph[q]);
+        A->gexec[q] = nullptr;
+        A->graph[q] = nullptr;
+    }
+}
+
 void adj_free(lbm_adjoint* A) {
-    if (A->gexec) (void)hipGraphExecDestroy(A->gexec);
-    if (A->graph) (void)hipGraphDestroy(A->graph);
+    drop_stage_graphs(A);
     if (A->sim) (void)hipStreamSynchronize(A->sim->stream);
+    if (A->aux) {
+        (void)hipStreamSynchronize(A->aux);
+        (void)hipStreamDestroy(A->aux);
+    }
+    if (A->ev_fork) (void)hipEventDestroy(A->ev_fork);
+    if (A->ev_join) (void)hipEventDestroy(A->ev_join);
     void* bufs[] = {A->ad_d, A->seg_descs_d, A->def_pop, A->def_out, A->init_pop, A->init_out,
                     A->ckpt_pop, A->ckpt_out, A->seg_pop, A->seg_out, A->abar[0], A->abar[1],
                     A->chibar, A->tile_acc, A->ring, A->ring_kn, A->seg_index, A->red};
@@ -335,12 +386,12 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
         if (e != hipSuccess) A->err = std::string("hipMalloc: ") + hipGetErrorString(e);
         return e == hipSuccess;
     };
-    if (!alloc((void**)&A->ad_d, sizeof(AdjDesc)) ||
-        !alloc((void**)&A->seg_descs_d, (size_t)K * sizeof(SimDesc)) ||
+    if (!alloc((void**)&A->ad_d, 2 * sizeof(AdjDesc)) ||
+        !alloc((void**)&A->seg_descs_d, 2 * (size_t)K * sizeof(SimDesc)) ||
         !alloc((void**)&A->def_pop, pb) || !alloc((void**)&A->def_out, ob) ||
         !alloc((void**)&A->init_pop, pb) || !alloc((void**)&A->init_out, ob) ||
         !alloc((void**)&A->ckpt_pop, pb * A->nseg) || !alloc((void**)&A->ckpt_out, ob * A->nseg) ||
-        !alloc((void**)&A->seg_pop, pb * (K + 1)) || !alloc((void**)&A->seg_out, ob * (K + 1)) ||
+        !alloc((void**)&A->seg_pop, 2 * pb * (K + 1)) || !alloc((void**)&A->seg_out, 2 * ob * (K + 1)) ||
         !alloc(&A->abar[0], pb) || !alloc(&A->abar[1], pb) || !alloc(&A->chibar, plane_b) ||
         !alloc((void**)&A->tile_acc, (size_t)A->atx * ny * 3 * sizeof(double)) ||
         !alloc((void**)&A->seg_index, 64) || !alloc((void**)&A->red, 8 * sizeof(double)))
@@ -360,18 +411,27 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     if (e == hipSuccess) e = hipMemcpy(A->def_out, s->outlet, ob, hipMemcpyDeviceToDevice);
     if (e == hipSuccess) e = hipMemcpy(A->init_pop, A->def_pop, pb, hipMemcpyDeviceToDevice);
     if (e == hipSuccess) e = hipMemcpy(A->init_out, A->def_out, ob, hipMemcpyDeviceToDevice);
-    // forward recomputation of a segment: step i reads buffer i and writes buffer i + 1
+    // forward recomputation of a segment into store q: step i reads buffer i and writes
+    // buffer i + 1 of that store
     if (e == hipSuccess) {
-        std::vector<SimDesc> sd((size_t)K, s->desc);
-        for (int i = 0; i < K; ++i) {
-            const int p = i & 1;
-            sd[i].pop[p] = A->seg_pop + (size_t)i * pb;
-            sd[i].pop[p ^ 1] = A->seg_pop + (size_t)(i + 1) * pb;
-            sd[i].outlet = A->seg_out + (size_t)i * ob;
-            sd[i].outlet_out = A->seg_out + (size_t)(i + 1) * ob;
+        std::vector<SimDesc> sd(2 * (size_t)K, s->desc);
+        for (int q = 0; q < 2; ++q) {
+            char* pop0 = A->seg_pop + (size_t)q * (K + 1) * pb;
+            char* out0 = A->seg_out + (size_t)q * (K + 1) * ob;
+            for (int i = 0; i < K; ++i) {
+                SimDesc& d = sd[(size_t)q * K + i];
+                const int p = i & 1;
+                d.pop[p] = pop0 + (size_t)i * pb;
+                d.pop[p ^ 1] = pop0 + (size_t)(i + 1) * pb;
+                d.outlet = out0 + (size_t)i * ob;
+                d.outlet_out = out0 + (size_t)(i + 1) * ob;
+            }
         }
         e = hipMemcpy(A->seg_descs_d, sd.data(), sd.size() * sizeof(SimDesc), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&A->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&A->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&A->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) return A->err = hipGetErrorString(e), bail(LBM_ERR_HIP);
     AdjDesc& ad = A->ad;
     std::memset(&ad, 0, sizeof(ad));
@@ -419,12 +479,7 @@ int lbm_adjoint_set_body(lbm_adjoint* A, const lbm_body* b) {
     A->body = *b;
     set_pose(A);
     A->fwd_done = A->bwd_done = false;
-    if (A->gexec) {  // the captured segment carries the row shift of the old pose
-        (void)hipGraphExecDestroy(A->gexec);
-        (void)hipGraphDestroy(A->graph);
-        A->gexec = nullptr;
-        A->graph = nullptr;
-    }
+    drop_stage_graphs(A);  // the captured stages carry the row shift of the old pose
     return upload_ad(A);
 }
 
@@ -524,29 +579,36 @@ int lbm_adjoint_backward(lbm_adjoint* A) {
     const int last = A->nseg - 1;
     AHIP_TRY(A, hipMemcpyAsync(A->seg_index, &last, sizeof(int), hipMemcpyHostToDevice, s->stream));
     AHIP_TRY(A, hipStreamSynchronize(s->stream));
+    // segments are swept last first; segment m's store is m & 1.  The recomputation of
+    // the last segment comes first, then stages m = nseg - 1 .. 1 (sweep m alongside the
+    // recomputation of m - 1), then the sweep over segment 0.
+    rc = enqueue_recompute(A, last & 1, s->stream);
+    if (rc) return rc;
     if (!A->graphs) {
-        for (int k = 0; k < A->nseg; ++k) {
-            rc = enqueue_segment(A);
+        for (int m = last; m >= 1; --m) {
+            rc = enqueue_stage(A, m & 1);
             if (rc) return rc;
         }
-        AHIP_TRY(A, hipStreamSynchronize(s->stream));
-        A->bwd_done = true;
-        return LBM_OK;
-    }
-    if (!A->gexec) {
-        AHIP_TRY(A, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_segment(A);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(s->stream, &g);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+    } else if (last >= 1) {
+        for (int q = 0; q < 2 && q < last; ++q) {
+            const int parity = (last - q) & 1;  // the first two stages, one of each parity
+            if (A->gexec[parity]) continue;
+            AHIP_TRY(A, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_stage(A, parity);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s->stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return afail(A, LBM_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+            A->graph[parity] = g;
+            AHIP_TRY(A, hipGraphInstantiate(&A->gexec[parity], g, nullptr, nullptr, 0));
         }
-        if (e != hipSuccess) return afail(A, LBM_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
-        A->graph = g;
-        AHIP_TRY(A, hipGraphInstantiate(&A->gexec, g, nullptr, nullptr, 0));
+        for (int m = last; m >= 1; --m) AHIP_TRY(A, hipGraphLaunch(A->gexec[m & 1], s->stream));
     }
-    for (int k = 0; k < A->nseg; ++k) AHIP_TRY(A, hipGraphLaunch(A->gexec, s->stream));
+    rc = enqueue_sweep(A, 0, s->stream);
+    if (rc) return rc;
     AHIP_TRY(A, hipStreamSynchronize(s->stream));
     A->bwd_done = true;
     return LBM_OK;
