@@ -765,7 +765,7 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
                 lbm_destroy(t);
                 return fail(s, LBM_ERR_HIP, "autotune: body");
             }
-            hipEvent_t e0, e1;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             float ms = 0.f;
             bool ok = hipMemcpyAsync(t->pop[0], s->pop[cur], s->pop_bytes, hipMemcpyDeviceToDevice,
                                      t->stream) == hipSuccess &&
@@ -778,8 +778,8 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
                       hipEventRecord(e1, t->stream) == hipSuccess &&
                       hipEventSynchronize(e1) == hipSuccess &&
                       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
             lbm_destroy(t);
             if (!ok) return fail(s, LBM_ERR_HIP, "autotune: timing run failed");
             const double us = 1e3 * ms / trial_steps;
@@ -1105,12 +1105,8 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
     }
     // one launch configuration for the whole batch; the defaults follow the single-grid
     // rules applied to the batch's total size
-    long long nodes = 0;
     size_t bytes = 0;
-    for (lbm_sim* s : b->sims) {
-        nodes += (long long)s->nx * s->ny;
-        bytes += s->pop_bytes;
-    }
+    for (lbm_sim* s : b->sims) bytes += s->pop_bytes;
     b->rows = bo.rows_per_tile ? bo.rows_per_tile : 1;
     b->nt = bo.store_mode == LBM_STORE_NONTEMPORAL ||
             (bo.store_mode == LBM_STORE_AUTO && 2 * bytes > (size_t(1) << 30));
