@@ -710,6 +710,9 @@ struct BodyStep {
     double qv[6];      // state of the next step: pose (X, Y, theta), then its velocities
     long long step, t_body;
     int boxM[4];       // participation box of that pose (filled by the thread that stores it)
+    // the previous state's step counters and P_in flag, staged for the lanes that use them
+    long long step_prev, t_prev;
+    int pin_valid;
 };
 
 __device__ __forceinline__ bool box_inside(const int a[4], const int b[4]) {
@@ -1024,11 +1027,28 @@ __device__ __forceinline__ void sum_slots(const double* __restrict__ slots, int 
                                           double red[][NRED], double* tot) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x < TILE_X) {  // uniform over each wave
+        // the thread's first slot is loaded straight into the accumulators, all its
+        // loads in flight before the first add waits (0 + v, as a sum from zero)
         double t[NRED];
+        int s = threadIdx.x;
+        if (s < nb) {
 #pragma unroll
-        for (int k = 0; k < NRED; ++k) t[k] = 0.0;
-        for (int s = threadIdx.x; s < nb; s += TILE_X)
-            for (int k = 0; k < NRED; ++k) t[k] += slots[(long long)s * NRED + k];
+            for (int k = 0; k < NRED; ++k) t[k] = gld(slots + (long long)s * NRED + k);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NRED; ++k) t[k] = 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) t[k] = 0.0 + t[k];
+        for (s += TILE_X; s < nb; s += TILE_X) {  // bodies of more than TILE_X tiles
+#pragma unroll
+            for (int h = 0; h < NRED; h += NRED / 2) {  // in halves: fewer live registers
+#pragma unroll
+                for (int k = h; k < h + NRED / 2; ++k) t[k] += gld(slots + (long long)s * NRED + k);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < NRED; ++k) {
             const double v = wave_sum(t[k]);
@@ -1055,23 +1075,35 @@ __device__ __forceinline__ int box_count(const int b[4]) { return (b[1] - b[0] +
 // carried across the interface by streaming (the momentum-exchange force of Eqs.
 // (25)-(27)); on the first step after the body is set the pre-collision momentum stands
 // in for the previous P_in.  The result is left in bs (LDS) for all threads; the work
-// runs in parallel lanes so that it needs no stack and few registers.
+// runs in parallel lanes so that it needs no stack and few registers.  slots are step
+// n - 1's partial slots; pbox is its participation box, which gives their count.
 __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[][NRED],
-                                            BodyStep& bs) {
+                                            BodyStep& bs, const double* slots, const int* pbox) {
     const BodyDev& B = *d.body;
     const BodyState& prev = B.st[p ^ 1];
-    // the lanes that advance a degree of freedom read its previous state first, so that
-    // these loads and the slot loads below return together
+    int nbox[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) nbox[i] = pbox[i];
+    // The lanes that advance a degree of freedom stage its previous state in the LDS
+    // fields they overwrite later (each lane its own): these loads return with the slot
+    // count's, and their registers are free again while the slots are read.
     const int k = threadIdx.x;
-    const int kk = k < 3 ? k : 0;
-    const double q_prev = prev.q[kk], v_prev = prev.v[kk], pin_prev = prev.pin_prev[kk];
-    const int pin_valid = prev.pin_valid;
-    const long long t_prev = prev.t_body, step_prev = prev.step;
-    sum_slots(d.partials + (long long)(p ^ 1) * d.part_stride, box_count(prev.part_box), red,
-              bs.tot);
+    if (k < 3) {  // one block, so that a single wait covers every load
+        const double q = gld(&prev.q[k]), v = gld(&prev.v[k]), pin = gld(&prev.pin_prev[k]);
+        const long long sp = gld(&prev.step), tp = gld(&prev.t_body);
+        const int pv = gld(&prev.pin_valid);
+        bs.qv[k] = q;
+        bs.qv[3 + k] = v;
+        bs.F[k] = pin;
+        bs.step_prev = sp;  // the same values from each of the three lanes
+        bs.t_prev = tp;
+        bs.pin_valid = pv;
+    }
+    sum_slots(slots, box_count(nbox), red, bs.tot);
     if (k < 3) {
+        const double q_prev = bs.qv[k], v_prev = bs.qv[3 + k], pin_prev = bs.F[k];
         double dp = 0.0;
-        if (B.imc) dp = bs.tot[3 + k] - (pin_valid ? pin_prev : bs.tot[6 + k]);
+        if (B.imc) dp = bs.tot[3 + k] - (bs.pin_valid ? pin_prev : bs.tot[6 + k]);
         bs.F[k] = bs.tot[k] + dp;
         const double F = B.mem == 1 ? bs.tot[9 + k] : bs.F[k];
         double q = q_prev, v = v_prev;
@@ -1079,7 +1111,7 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
             if (B.mode == MODE_IMPOSED_SIN) {
                 if (k == 1) {
                     const double w = 6.283185307179586476925286766559 * B.freq;
-                    const double ph = w * (double)(t_prev + 1) + B.phase;
+                    const double ph = w * (double)(bs.t_prev + 1) + B.phase;
                     q = B.y0 + B.amp * sin(ph);
                     v = w * B.amp * cos(ph);
                 }
@@ -1092,8 +1124,8 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
         bs.qv[k] = q;
         bs.qv[3 + k] = v;
     } else if (k == 3) {
-        bs.step = step_prev + 1;
-        bs.t_body = t_prev + 1;
+        bs.step = bs.step_prev + 1;
+        bs.t_body = bs.t_prev + 1;
     }
     __syncthreads();
 }
@@ -1155,6 +1187,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     // The step's scalars, then the participation box and whether this step's state is
     // final already, then the first row's populations.
     const TileScalars<T> ts = tile_scalars<S>(d, p);
+    const double* prev_slots = d.partials + (long long)(p ^ 1) * d.part_stride;
     // The box is read with vector-memory (buffer) loads whose values stay in vector
     // registers until the pull has been issued: a uniform load result is otherwise
     // moved to scalar registers, with a wait for it, where it is loaded, and a scalar
@@ -1196,13 +1229,14 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     const double* pose;
     if (fresh) {
         if (threadIdx.x < 3) {
-            pose_set[threadIdx.x] = B.st[p].q[threadIdx.x];
-            pose_set[3 + threadIdx.x] = B.st[p].v[threadIdx.x];
+            const double q = gld(&B.st[p].q[threadIdx.x]), v = gld(&B.st[p].v[threadIdx.x]);
+            pose_set[threadIdx.x] = q;
+            pose_set[3 + threadIdx.x] = v;
         }
         __syncthreads();
         pose = pose_set;
     } else {
-        derive_body(d, p, red, bs);
+        derive_body(d, p, red, bs, prev_slots, B.st[p ^ 1].part_box);
         pose = bs.qv;
     }
 #pragma unroll
@@ -1258,7 +1292,8 @@ __device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
     if (B.st[p].fresh) return;  // uniform
-    derive_body(d, p, red, bs);
+    derive_body(d, p, red, bs, d.partials + (long long)(p ^ 1) * d.part_stride,
+                B.st[p ^ 1].part_box);
     if (threadIdx.x == 0) {
         const BodyState& prev = B.st[p ^ 1];
         int exact[4];
