@@ -235,6 +235,22 @@ def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb):
     run_pair(gpu, spec, b, steps=8, seed=99, check_every=2)
 
 
+@pytest.mark.parametrize("tile", [256, 512])
+def test_body_over_more_tiles_than_a_workgroup_has_threads_fp64(gpu, tile):
+    """A disc of diameter 260 on a 300x300 grid: with one row per tile its participation
+    box holds about 540 (256-column tiles) or 270 (512-column) tiles, more than the 256
+    threads that add the slots, so each of them adds several.  Three steps between
+    synchronising calls: the derivation inside the step and the flush both run."""
+    nx, ny = 300, 300
+    _flush("large body tile %d" % tile)
+    spec = spec_of(nx, ny, BCS["channel"], u_wall=UWALL, u_conv=0.04)
+    spec["tile_width"] = tile
+    b = W.fixed_disc(260.0, 150.3, 149.6)
+    b.update(mode="free", free_mask=7, mass=5e6, inertia=5e9, k=(0.01, 0.01, 0.0),
+             q0=(150.3, 149.6, 0.0))
+    run_pair(gpu, spec, b, steps=9, seed=5, check_every=3)
+
+
 def test_circle_ties_are_classified_like_the_oracle(gpu):
     """Disc of radius 10 centred on a node: the 12 nodes lying exactly on the circle
     (d^2 == R^2) count as inside on both sides (317 nodes in all)."""
