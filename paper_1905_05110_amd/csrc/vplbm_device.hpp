@@ -710,9 +710,10 @@ struct BodyStep {
     double qv[6];      // state of the next step: pose (X, Y, theta), then its velocities
     long long step, t_body;
     int boxM[4];       // participation box of that pose (filled by the thread that stores it)
-    // the previous state's step counters and P_in flag, staged for the lanes that use them
-    long long step_prev, t_prev;
-    int pin_valid;
+    // the previous state's step counters and P_in flag, staged by lanes 0-2 (one copy
+    // each, so that no two lanes write one location)
+    long long step_prev[3], t_prev[3];
+    int pin_valid[3];
 };
 
 __device__ __forceinline__ bool box_inside(const int a[4], const int b[4]) {
@@ -1095,15 +1096,15 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
         bs.qv[k] = q;
         bs.qv[3 + k] = v;
         bs.F[k] = pin;
-        bs.step_prev = sp;  // the same values from each of the three lanes
-        bs.t_prev = tp;
-        bs.pin_valid = pv;
+        bs.step_prev[k] = sp;
+        bs.t_prev[k] = tp;
+        bs.pin_valid[k] = pv;
     }
     sum_slots(slots, box_count(nbox), red, bs.tot);
     if (k < 3) {
         const double q_prev = bs.qv[k], v_prev = bs.qv[3 + k], pin_prev = bs.F[k];
         double dp = 0.0;
-        if (B.imc) dp = bs.tot[3 + k] - (bs.pin_valid ? pin_prev : bs.tot[6 + k]);
+        if (B.imc) dp = bs.tot[3 + k] - (bs.pin_valid[k] ? pin_prev : bs.tot[6 + k]);
         bs.F[k] = bs.tot[k] + dp;
         const double F = B.mem == 1 ? bs.tot[9 + k] : bs.F[k];
         double q = q_prev, v = v_prev;
@@ -1111,7 +1112,7 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
             if (B.mode == MODE_IMPOSED_SIN) {
                 if (k == 1) {
                     const double w = 6.283185307179586476925286766559 * B.freq;
-                    const double ph = w * (double)(bs.t_prev + 1) + B.phase;
+                    const double ph = w * (double)(bs.t_prev[k] + 1) + B.phase;
                     q = B.y0 + B.amp * sin(ph);
                     v = w * B.amp * cos(ph);
                 }
@@ -1124,8 +1125,8 @@ __device__ __forceinline__ void derive_body(const SimDesc& d, int p, double red[
         bs.qv[k] = q;
         bs.qv[3 + k] = v;
     } else if (k == 3) {
-        bs.step = bs.step_prev + 1;
-        bs.t_body = bs.t_prev + 1;
+        bs.step = bs.step_prev[0] + 1;  // staged before the slot sums' barriers
+        bs.t_body = bs.t_prev[0] + 1;
     }
     __syncthreads();
 }
