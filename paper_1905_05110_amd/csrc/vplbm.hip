@@ -62,8 +62,8 @@ static int dispatch_row_shift(const int boxM[4], int tiles_y) {
 }
 
 static void drop_graph(lbm_sim* s) {
-    if (s->gexec) hipGraphExecDestroy(s->gexec);
-    if (s->graph) hipGraphDestroy(s->graph);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
     s->gexec = nullptr;
     s->graph = nullptr;
 }
@@ -154,14 +154,14 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
 static void free_sim(lbm_sim* s) {
     drop_graph(s);
     if (s->own_pop) {
-        if (s->pop[0]) hipFree(s->pop[0]);
-        if (s->pop[1]) hipFree(s->pop[1]);
+        if (s->pop[0]) (void)hipFree(s->pop[0]);
+        if (s->pop[1]) (void)hipFree(s->pop[1]);
     }
     void* bufs[] = {s->outlet, s->body_d, s->partials, s->hist, s->flag, s->staging,
                     s->desc_d};
     for (void* b : bufs)
-        if (b) hipFree(b);
-    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+        if (b) (void)hipFree(b);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
 
@@ -379,7 +379,8 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
 int lbm_destroy(lbm_sim* s) {
     if (!s) return LBM_ERR_ARG;
     if (s->in_batch) return reject_member(s);
-    hipStreamSynchronize(s->stream);
+    // an error of the work still queued is not reported here: the handle goes either way
+    (void)hipStreamSynchronize(s->stream);
     free_sim(s);
     return LBM_OK;
 }
@@ -517,7 +518,7 @@ static int capture_graph(lbm_sim* s) {
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     s->host_step = saved;
     if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(s, LBM_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
@@ -557,24 +558,35 @@ int lbm_step(lbm_sim* s, int64_t n) {
 int lbm_step_timed(lbm_sim* s, int64_t n, double* kernel_ms, double* region_ms) {
     if (!s || n < 0) return fail(s, LBM_ERR_ARG, "bad argument");
     if (s->in_batch) return reject_member(s);
-    std::vector<hipEvent_t> ev(2 * (size_t)n + 2);
-    for (auto& e : ev) HIP_TRY(s, hipEventCreate(&e));
-    HIP_TRY(s, hipEventRecord(ev[0], s->stream));
+    // Every event created here is destroyed on every way out; the first failure is the
+    // one reported, and no timing is returned after one.
+    std::vector<hipEvent_t> ev;
+    ev.reserve(2 * (size_t)n + 2);
     int rc = LBM_OK;
+    auto check = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && rc == LBM_OK)
+            rc = fail(s, LBM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    for (size_t i = 0; i < 2 * (size_t)n + 2 && rc == LBM_OK; ++i) {
+        hipEvent_t e = nullptr;
+        check(hipEventCreate(&e), "hipEventCreate");
+        if (rc == LBM_OK) ev.push_back(e);
+    }
+    if (rc == LBM_OK) check(hipEventRecord(ev[0], s->stream), "hipEventRecord");
     for (int64_t k = 0; k < n && rc == LBM_OK; ++k) rc = launch_step(s, ev[2 + 2 * k], ev[3 + 2 * k]);
-    HIP_TRY(s, hipEventRecord(ev[1], s->stream));
-    HIP_TRY(s, hipEventSynchronize(ev[1]));
+    if (rc == LBM_OK) check(hipEventRecord(ev[1], s->stream), "hipEventRecord");
+    if (rc == LBM_OK) check(hipEventSynchronize(ev[1]), "hipEventSynchronize");
     double ksum = 0.0;
-    float ms = 0.f;
-    for (int64_t k = 0; k < n; ++k) {
-        hipEventElapsedTime(&ms, ev[2 + 2 * k], ev[3 + 2 * k]);
+    float ms = 0.f, region = 0.f;
+    for (int64_t k = 0; k < n && rc == LBM_OK; ++k) {
+        check(hipEventElapsedTime(&ms, ev[2 + 2 * k], ev[3 + 2 * k]), "hipEventElapsedTime");
         ksum += ms;
     }
-    hipEventElapsedTime(&ms, ev[0], ev[1]);
-    for (auto& e : ev) hipEventDestroy(e);
+    if (rc == LBM_OK) check(hipEventElapsedTime(&region, ev[0], ev[1]), "hipEventElapsedTime");
+    for (auto& e : ev) (void)hipEventDestroy(e);  // nothing to recover from here
     if (rc) return rc;
     if (kernel_ms) *kernel_ms = ksum;
-    if (region_ms) *region_ms = ms;
+    if (region_ms) *region_ms = region;
     return LBM_OK;
 }
 

@@ -337,6 +337,24 @@ def test_same_configuration_is_deterministic(gpu):
     assert np.array_equal(runs[0][1]["fvp"], runs[1][1]["fvp"])
 
 
+def test_timed_steps_match_plain_steps(gpu):
+    """lbm_step_timed runs the same eager launches as lbm_step, bracketed by events: the
+    state is bitwise the plain run's, the step index advances, and the kernel time is
+    positive and within the region's."""
+    _flush("timed steps")
+    wl = W.imposed_oscillation(storage="fp32", nx=600, ny=90, D=24.0)
+    a = gpu.Sim(wl["spec"], wl["body"])
+    b = gpu.Sim(wl["spec"], wl["body"])
+    a.step(7)
+    kms, rms = b.step_timed(7)
+    assert b.step_index() == a.step_index() == 7
+    assert 0.0 < kms <= rms * 1.001
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(a.forces()["fvp"], b.forces()["fvp"])
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("tile", [256, 512])
 def test_flushes_do_not_change_results(gpu, tile):
     """A synchronising call makes the pending body state final with a one-workgroup
