@@ -53,11 +53,16 @@ static int upload_desc(lbm_sim* s) {
 
 // First tile row in dispatch order.  Tiles that meet the body take longer than the
 // others; dispatched among the last workgroups they would extend the end of the grid.
-// Their rows are placed a sixteenth of the grid into the order, not at its start: the
-// rotation is fixed while a captured graph is replayed, and a body that has since moved
-// to lower rows then still has its tiles dispatched early rather than wrapped to the end.
-static int dispatch_row_shift(const int boxM[4], int tiles_y) {
-    const int r = boxM[2] - tiles_y / 16;
+// Their rows are placed a little into the order, not at its start: the rotation is fixed
+// while a captured graph is replayed, and a body that has since moved to lower rows then
+// still has its tiles dispatched early rather than wrapped to the end.  How far in was
+// measured on the free-VIV grid: an eighth of the rows for 32- and 64-bit populations
+// (1-1.5 % faster than a sixteenth), a sixteenth for 16-bit ones (whose shorter tiles
+// lost 1 % at an eighth).
+static int dispatch_row_shift(const lbm_sim* s, const int boxM[4]) {
+    const int tiles_y = s->desc.tiles_y;
+    const bool narrow = s->storage == LBM_FP16_OFS || s->storage == LBM_BF16_OFS;
+    const int r = boxM[2] - tiles_y / (narrow ? 16 : 8);
     return ((r % tiles_y) + tiles_y) % tiles_y;
 }
 
@@ -463,7 +468,7 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     // a step takes part by the box of the state before it: the other slot starts as a
     // copy of this one
     B.st[p ^ 1] = st;
-    const int shift = dispatch_row_shift(st.boxM, s->desc.tiles_y);
+    const int shift = dispatch_row_shift(s, st.boxM);
     if (s->row_shift != shift) {  // captured launches carry the row shift
         s->row_shift = shift;
         drop_graph(s);
@@ -693,7 +698,7 @@ static int apply_launch_config(lbm_sim* s, int rows, bool nt, int tile_w) {
     body_tiles(s->nx, s->ny, rows, tile_w, B, st.q[0], st.q[1], st.boxM);
     body_tiles(s->nx, s->ny, rows, tile_w, B, before.q[0], before.q[1], before.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = before.boxM[k];
-    s->row_shift = dispatch_row_shift(st.boxM, s->desc.tiles_y);
+    s->row_shift = dispatch_row_shift(s, st.boxM);
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
     int rc = upload_desc(s);
     if (rc) return rc;
@@ -900,7 +905,7 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     }
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(BodyDev), hipMemcpyHostToDevice));
     s->has_body = B.active != 0;
-    s->row_shift = dispatch_row_shift(B.st[s->host_step & 1].boxM, s->desc.tiles_y);
+    s->row_shift = dispatch_row_shift(s, B.st[s->host_step & 1].boxM);
     if (!s->has_body) s->rec_end = s->drained = std::max(s->drained, s->host_step);
     HIP_TRY(s, hipMemset(s->flag, 0, sizeof(int)));
     drop_graph(s);
