@@ -1176,7 +1176,7 @@ __device__ __forceinline__ void store_state(BodyState& cur, const BodyState& pre
 // needed: the kernel boundary orders producer and consumer (on this multi-XCD part such
 // a fence would write back the whole L2).
 // The caller maps workgroups to tiles (the host rotates the rows so that those of the
-// body are dispatched early, a sixteenth of the grid in: their longer work then overlaps
+// body are dispatched early, a little into the grid: their longer work then overlaps
 // the rest of the grid instead of extending the end of the kernel).
 template <class S, int ROWS, bool NT, int TW>
 __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p) {

@@ -66,7 +66,7 @@ struct lbm_sim {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     bool in_batch = false;  // member of an lbm_batch: stepped, configured and freed by it
-    int row_shift = 0;      // first tile row dispatched (the body's rows come a sixteenth of the grid later)
+    int row_shift = 0;      // first tile row dispatched (the body's rows come a little later)
 };
 
 #define HIP_TRY(sim, expr)                                                             \
