@@ -377,6 +377,97 @@ def test_outflow_lets_a_disturbance_leave(orc):
     assert d1 < 0.05 * d0
 
 
+OUTFLOW_DIRS = (3, 6, 7)  # the directions whose source lies beyond the east side
+
+
+def _outflow_case(orc, u_conv, seed):
+    """A channel (inlet, convective outlet, symmetry planes) in a random near-rest state
+    with a random outflow memory."""
+    spec = W.channel_spec(17, 9, 0.04, 0.6)
+    spec["u_conv"] = u_conv
+    sim = orc.OracleSim(spec)
+    rng = np.random.default_rng(seed)
+    sim.set_populations(W.random_populations(17, 9, seed=seed, amp=0.1))
+    O0 = np.array([W.LATTICE_WEIGHTS[a] for a in OUTFLOW_DIRS])[:, None] * \
+        (1.0 + 0.1 * rng.uniform(-1.0, 1.0, (3, 9)))
+    sim.set_outlet(O0)
+    return sim, O0
+
+
+def test_outflow_without_convection_keeps_its_memory(orc):
+    """Sec. 3.1 outlet, df/dt + U_c df/dx = 0: with U_c = 0 the incoming populations of
+    the east column do not change in time, whatever the interior does.  Over 60 steps
+    of a random interior the memory, and what the east column pulls, stay exactly at
+    their initial values (a zero-gradient outlet would copy the interior instead)."""
+    sim, O0 = _outflow_case(orc, 0.0, 5)
+    sim.step(60)
+    assert np.array_equal(sim.outlet, O0)
+    for j in range(9):
+        P = sim.pull_node(16, j)
+        assert np.array_equal(P[list(OUTFLOW_DIRS)], O0[:, j])
+
+
+def test_outflow_with_fast_convection_copies_the_inner_value(orc):
+    """U_c -> infinity: the time derivative drops out and df/dx = 0, so the east column
+    takes what node nx - 2 pulls for the same direction (to round-off, at U_c = 1e12)."""
+    sim, _ = _outflow_case(orc, 1e12, 6)
+    sim.step(30)
+    for j in range(9):
+        P, Q = sim.pull_node(16, j), sim.pull_node(15, j)
+        for a in OUTFLOW_DIRS:
+            assert abs(P[a] - Q[a]) <= 1e-11 * abs(Q[a])
+
+
+@pytest.mark.parametrize("u_conv", [0.05, 0.3, 2.0])
+def test_outflow_is_implicit_euler_in_time(orc, u_conv):
+    """With the interior frozen, the outlet value relaxes to the inner value Q by
+    dP/dt = -U_c (P - Q); the implicit (backward) Euler step with dt = dx = 1 multiplies
+    P - Q by 1/(1 + U_c) each step (an explicit step would give 1 - U_c, a swap of the
+    two weights U_c/(1 + U_c)).  Iterating the oracle's own pull of the east column on a
+    fixed state gives that factor at three values of U_c."""
+    sim, _ = _outflow_case(orc, u_conv, 7)
+    for j in (0, 4, 8):  # bottom corner, interior, top corner
+        Q = sim.pull_node(15, j)[list(OUTFLOW_DIRS)]
+        prev = sim.pull_node(16, j)[list(OUTFLOW_DIRS)] - Q
+        for _ in range(5):
+            out = sim.outlet.copy()
+            out[:, j] = sim.pull_node(16, j)[list(OUTFLOW_DIRS)]
+            sim.set_outlet(out)  # the memory update of one step, interior held fixed
+            cur = sim.pull_node(16, j)[list(OUTFLOW_DIRS)] - Q
+            assert np.allclose(cur, prev / (1.0 + u_conv), rtol=1e-12, atol=1e-17)
+            prev = cur
+
+
+def test_fp32_rounding_model_of_the_imposed_oscillation(orc):
+    """The bound on FP32 velocities after the 2000-step imposed oscillation (1e-5 U0).
+    FP32 rounds each stored value to a relative 2^-24.  Independent rounding errors of
+    that size, applied to every stored population at every step of the FP64 run, move
+    the velocity field by far less than the bound (measured 2.5e-6 U0): an unbiased FP32
+    path can meet it.  The same relative size as a coherent bias (every stored offset
+    from the inflow equilibrium scaled by 1 + 2^-24, as a constant rounded the same way
+    at every node and step does) moves it by more than 5e-5 U0 (measured 1.2e-4): the
+    flow amplifies coherent errors, and the bound is tight enough to catch one."""
+    wl = W.imposed_oscillation(storage="fp64")
+    U0, eps = wl["U0"], 2.0 ** -24
+    fref = orc.feq(1.0, U0, 0.0)[:, None, None]
+
+    def run(perturb):
+        o = orc.OracleSim(wl["spec"], wl["body"])
+        for _ in range(wl["steps"]):
+            o.step(1)
+            if perturb is not None:
+                o.set_populations(perturb(o.get_populations()))
+        return o.fields()
+
+    rng = np.random.default_rng(2)
+    ref = run(None)
+    noise = run(lambda f: f * (1.0 + eps * rng.uniform(-1.0, 1.0, f.shape)))
+    bias = run(lambda f: fref + (f - fref) * (1.0 + eps))
+    du = lambda a: max(np.abs(a[1] - ref[1]).max(), np.abs(a[2] - ref[2]).max()) / U0
+    assert du(noise) <= 1e-5
+    assert du(bias) >= 5e-5
+
+
 def test_taylor_green_decay_rate(orc):
     """u = U(-cos kx sin ky, sin kx cos ky) decays as exp(-2 nu k^2 t)."""
     tau = 0.8
