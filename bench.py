@@ -1,28 +1,38 @@
 """Throughput of the VP-LBM time step on one MI355X.
 
-Workload: the free vortex-induced-vibration run, 2048x1024 channel, disc D = 40 on a
-transverse spring (mass ratio 10, reduced velocity 5, Re = 150), FP32 populations.
-A step is one full fluid-structure step (pull-stream, penalization, MRT collision,
-FP64 force/torque reduction, RK4 body update) over the whole grid, all on the GPU.
+Default workload (``--workload batch_sweep``): 64 independent free vortex-induced-
+vibration runs of uneven size (ny drawn from U{128..512} with seed 0, nx = 2 ny,
+D = ny/12, reduced velocity 2 to 12, mass ratio 10, Re = 150; 15.1 M nodes, 2.2 GB of
+FP32 populations, far beyond the 256 MB Infinity Cache), all advanced by one kernel
+launch per step.  A step is one full fluid-structure step of every run (pull-stream,
+penalization, MRT collision, FP64 force/torque reduction, RK4 body update), all on the
+GPU.
+
+The timed region starts from a seeded random near-rest state, w_a (1 + 0.02 xi) with
+xi ~ U(-1, 1) (the same generator as the parity tests), written into every run just
+before it, whatever the warm-up was: no stored offset is then exactly zero (the memory
+system moves lines of zeros faster than lines of data, so a state that still holds the
+uniform inflow would overstate the rate).
 
 Prints one JSON line: MLUPS (million lattice-node updates per second) of the timed
 region, the step kernel's achieved HBM bandwidth against the 8 TB/s peak, and the FP64
-CPU oracle timed on a bounded sample of the same workload on the host cores.  A step is
-exactly one kernel launch (replayed from captured HIP graphs), so the kernel's average
-duration is the timed region's event-measured time divided by the number of launches.
+CPU oracle timed on a bounded sample of the same workload on the host cores (all the
+cores of the GPU's share and one core).  A step is exactly one kernel launch (replayed
+from captured HIP graphs), so the kernel's average duration is the timed region's
+event-measured time divided by the number of launches.
 
-``--workload batch_sweep`` times the batched path instead: 64 free-VIV runs of uneven
-size (ny drawn from U{128..512} with seed 0, nx = 2 ny, D = ny/12, U_r from 2 to 12),
-all advanced by one launch per step.  ``--accuracy-steps N`` then also runs the sweep
-for N steps in every storage precision and reports, per precision, the relative error
-of each run's mean drag coefficient and RMS lift coefficient over the second half of
-the run against the FP64 runs.
-
-``--workload adjoint`` times the reverse-mode path: gradient of the time-averaged drag
-coefficient of a fixed disc (D = 32, Re = 100, tanh indicator, 1024x512 channel) over
-4000 steps with a checkpoint every 100, with respect to the indicator field and the
-disc centre.  The value is the adjoint/forward time ratio (backward sweep including
-the recomputation, over the forward run including the checkpoint copies).
+Other workloads:
+  ``free_viv``       2048x1024 channel, disc D = 40 on a transverse spring (151 MB in
+                     FP32: largely resident in the Infinity Cache);
+  ``sedimentation``  1024x4096 closed box, a disc D = 32 of density ratio 1.5 falling
+                     free in x, y and theta (302 MB in FP32);
+  ``roofline``       8192x8192 channel with a fixed disc D = 512 (4.8 GB in FP32);
+  ``adjoint``        reverse-mode gradient of the time-averaged drag of a fixed disc
+                     (1024x512, 4000 steps, a checkpoint every 100): the value is the
+                     adjoint/forward time ratio.
+``--accuracy-steps N`` (batch_sweep) also runs the sweep for N steps in every storage
+precision and reports the relative error of each run's mean drag and RMS lift
+coefficients over the second half of the run against the FP64 runs.
 """
 import argparse
 import json
@@ -35,16 +45,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}  # 9 reads + 9 writes
+CPU_SHARE = 16  # host cores that go with one GPU of the box
+STATE_SEED, STATE_AMP = 2024, 0.02
+DTYPE = {"fp32": "f32", "fp64": "f64", "fp16": "f32 (fp16 storage)", "bf16": "f32 (bf16 storage)"}
+DATA = ("synthetic: timed from a seeded random near-rest state w_a (1 + 0.02 xi), "
+        "xi ~ U(-1, 1), seed %d, written into every run before the timed region; no dataset"
+        % STATE_SEED)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="free_viv", choices=("free_viv", "batch_sweep", "adjoint"))
+    ap.add_argument("--workload", default="batch_sweep",
+                    choices=("batch_sweep", "free_viv", "sedimentation", "roofline", "adjoint"))
     ap.add_argument("--accuracy-steps", type=int, default=0,
                     help="batch_sweep: also compare storages over this many steps")
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: the workload's default)")
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="fp32", choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--graph-steps", type=int, default=64,
                     help="steps per captured HIP graph in the timed region (0: eager launches)")
@@ -52,9 +69,14 @@ def parse():
     ap.add_argument("--store", default="auto", choices=("auto", "plain", "nontemporal"))
     ap.add_argument("--tile-width", type=int, default=0, choices=(0, 256, 512),
                     help="columns per tile (0: autotune)")
+    ap.add_argument("--order", default="auto",
+                    choices=("auto", "given", "largest_first", "interleaved"),
+                    help="batch_sweep: tile schedule order (auto: autotune)")
+    ap.add_argument("--layout", default="auto", choices=("auto", "rows", "planes"))
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU time of each oracle sample (all cores, then one core)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 256 MiB first (scale for HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.txt"),
@@ -62,33 +84,66 @@ def parse():
     return ap.parse_args()
 
 
-def split_warmup(warmup, graph_steps):
-    """Untimed steps before and after the launch configuration is chosen: the
-    autotuner times its candidates from the developed flow, and the steps after it
-    capture the graphs of the timed region.  Together they are the requested warm-up."""
-    post = min(warmup // 2, max(2 * graph_steps, 128))
-    return warmup - post, post
+DEFAULT_STEPS = {"batch_sweep": 4000, "free_viv": 20000, "sedimentation": 10000,
+                 "roofline": 400, "adjoint": 0}
 
 
-def cpu_baseline(wl, target_seconds):
-    """FP64 CPU oracle on the same grid for a bounded number of steps."""
+def pinned(args):
+    return args.rows != 0 or args.store != "auto" or args.tile_width != 0 or \
+        (args.workload == "batch_sweep" and args.order != "auto")
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def oracle_rate(members, target_seconds, threads):
+    """FP64 CPU oracle over the given runs (smallest first) for a bounded time: returns
+    (MLUPS, steps per run, runs used, seconds, threads).  The first step of every run is
+    not counted; that of the first run sizes the sample."""
     from oracle import oracle as orc
-    cores = min(len(os.sched_getaffinity(0)), 16)
-    orc.set_threads(cores)
-    sim = orc.OracleSim(wl["spec"], wl["body"])
-    sim.step(2)  # warm-up
-    t0 = time.perf_counter()
-    sim.step(3)
-    per_step = (time.perf_counter() - t0) / 3
-    n = max(3, min(400, int(target_seconds / per_step)))
-    t0 = time.perf_counter()
-    sim.step(n)
-    dt = time.perf_counter() - t0
-    nodes = wl["spec"]["nx"] * wl["spec"]["ny"]
-    return {"value": round(nodes * n / dt / 1e6, 2), "unit": "MLUPS", "cores": orc.max_threads(),
-            "kind": "oracle",
-            "sample": "%d steps of the %dx%d grid (FP64 oracle, %.1f s)" % (
-                n, wl["spec"]["nx"], wl["spec"]["ny"], dt)}
+    orc.set_threads(threads)
+    ordered = sorted(members, key=lambda w: w["spec"]["nx"] * w["spec"]["ny"])
+    total_nodes = sum(w["spec"]["nx"] * w["spec"]["ny"] for w in ordered)
+    steps, done, dt, used = None, 0, 0.0, 0
+    for w in ordered:
+        nodes = w["spec"]["nx"] * w["spec"]["ny"]
+        sim = orc.OracleSim(w["spec"], w["body"])
+        t0 = time.perf_counter()
+        sim.step(1)  # first touch of the arrays: not counted
+        if steps is None:
+            per_node = (time.perf_counter() - t0) / nodes
+            steps = max(2, min(200, int(target_seconds / (per_node * total_nodes))))
+        t0 = time.perf_counter()
+        sim.step(steps)
+        dt += time.perf_counter() - t0
+        done += nodes * steps
+        used += 1
+        del sim
+        if dt > target_seconds:
+            break
+    return done / dt / 1e6, steps, used, dt, orc.max_threads()
+
+
+def cpu_baseline(members, target_seconds, label):
+    model, avail = cpu_info()
+    cores = min(avail, CPU_SHARE)
+    v_all, steps, used, dt, threads = oracle_rate(members, target_seconds, cores)
+    v_one, steps1, used1, dt1, _ = oracle_rate(members, target_seconds, 1)
+    return {"value": round(v_all, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "%d steps of %d of the %s (FP64 oracle, %.1f s on %d threads)" % (
+                steps, used, label, dt, threads),
+            "single_core_value": round(v_one, 3),
+            "single_core_sample": "%d steps of %d of the %s (%.1f s)" % (steps1, used1, label, dt1),
+            "cpu_model": model, "cores_visible": avail, "cores_share": CPU_SHARE}
 
 
 def kernel_source_hash(storage):
@@ -101,41 +156,49 @@ def kernel_source_hash(storage):
     return h.hexdigest()[:16]
 
 
-def traffic_for(path, storage, nx, ny, rows, nt, tile):
+def traffic_for(path, key):
     """Measured HBM bytes per launch from the rocprofv3 counter summary, if one was
-    recorded for this configuration and for the kernel sources as they are now."""
+    recorded for this workload and launch configuration and for the kernel sources as
+    they are now.  Lines: traffic <key fields...> <source-hash> <bytes-per-launch>."""
     if not path or not os.path.exists(path):
         return None
-    want = "%s %d %d %d %d %d" % (storage, nx, ny, rows, int(bool(nt)), tile)
-    src = kernel_source_hash(storage)
+    want = key.split()
+    src = kernel_source_hash(want[1])
     for line in open(path):
         f = line.split()
-        # traffic <storage> <nx> <ny> <rows> <nt> <tile> <source-hash> <bytes-per-launch>
-        if len(f) == 9 and f[0] == "traffic" and " ".join(f[1:7]) == want and f[7] == src:
-            return int(f[8])
+        if len(f) == len(want) + 3 and f[0] == "traffic" and f[1:-2] == want and f[-2] == src:
+            return int(f[-1])
     return None
 
 
-def cpu_baseline_batch(sweep, target_seconds):
-    """FP64 CPU oracle on the sweep's runs, smallest first, for a bounded time."""
-    from oracle import oracle as orc
-    cores = min(len(os.sched_getaffinity(0)), 16)
-    orc.set_threads(cores)
-    nodes_done, dt, used = 0, 0.0, []
-    for w in sorted(sweep, key=lambda w: w["spec"]["nx"] * w["spec"]["ny"]):
-        sim = orc.OracleSim(w["spec"], w["body"])
-        sim.step(1)
-        t0 = time.perf_counter()
-        sim.step(20)
-        dt += time.perf_counter() - t0
-        nodes_done += w["spec"]["nx"] * w["spec"]["ny"] * 20
-        used.append(w["name"])
-        if dt > target_seconds:
-            break
-    return {"value": round(nodes_done / dt / 1e6, 2), "unit": "MLUPS", "cores": orc.max_threads(),
-            "kind": "oracle",
-            "sample": "20 steps of each of the %d smallest runs of the sweep (FP64 oracle, %.1f s)"
-                      % (len(used), dt)}
+def seeded_state(sim):
+    """The timed region's start: w_a (1 + amp xi) on every node."""
+    from paper_1905_05110_amd import workloads as W
+    f = W.random_populations(sim.nx, sim.ny, seed=STATE_SEED, amp=STATE_AMP)
+    sim.set_populations(f)
+
+
+def roofline(args, bytes_per_launch, avg_kernel_s, kernel, traffic_key):
+    achieved = bytes_per_launch / avg_kernel_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(args.traffic, traffic_key), "kernel": kernel,
+            "avg_kernel_us": round(avg_kernel_s * 1e6, 3),
+            "algorithmic_bytes_per_launch": bytes_per_launch, "traffic_key": traffic_key}
+
+
+def timed(stream, run, steps):
+    import torch
+    print("timed %d steps" % steps, file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), wall
 
 
 def sweep_statistics(batch, sweep, steps):
@@ -182,76 +245,144 @@ def batch_accuracy(args, vplbm, W):
     return out
 
 
+def split_warmup(warmup, graph_steps):
+    """Untimed steps before and after the launch configuration is chosen (the steps
+    after it capture the graphs of the timed region); together the requested warm-up."""
+    post = min(warmup // 2, max(2 * graph_steps, 64))
+    return warmup - post, post
+
+
 def run_batch(args):
     import torch
     from paper_1905_05110_amd import workloads as W
     from paper_1905_05110_amd import vplbm
 
+    steps = args.steps or DEFAULT_STEPS["batch_sweep"]
     sweep = W.batch_sweep(storage=args.storage)
     members = [(w["spec"], w["body"]) for w in sweep]
     nodes = sum(s["nx"] * s["ny"] for s, _ in members)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        rows = args.rows if args.rows else 0
-        batch = vplbm.Batch(members, storage=args.storage, rows=rows, store=args.store,
+        batch = vplbm.Batch(members, storage=args.storage, rows=args.rows, store=args.store,
                             history_cap=4096, stream=stream.cuda_stream,
-                            tile_width=args.tile_width)
-        tuned = None
+                            tile_width=args.tile_width, layout=args.layout,
+                            order="largest_first" if args.order == "auto" else args.order)
         w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
         print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
         batch.step(w_pre)
         batch.sync()
-        if not args.no_autotune and args.rows == 0 and args.store == "auto" and not args.tile_width:
+        for m in batch.sims:
+            seeded_state(m)
+        tuned = None
+        if not args.no_autotune and not pinned(args):
             print("autotune", file=sys.stderr, flush=True)
             tuned = batch.autotune(trial_steps=20)
         b_rows, b_nt, b_tile = batch.sims[0].launch_config()
+        order = batch.order_name()
         if args.graph_steps:
             batch.set_graph_steps(args.graph_steps)
         batch.step(w_post)
         batch.sync()
-        torch.cuda.synchronize()
-        print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        batch.step(args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        region_ms = e0.elapsed_time(e1)
+        for m in batch.sims:
+            seeded_state(m)
+        region_ms, wall = timed(stream, batch.step, steps)
         batch.sync()
+        layout = batch.sims[0].layout_name()
         batch.close()
-    ms_per_step = region_ms / args.steps
-    mlups = nodes * args.steps / (region_ms * 1e-3) / 1e6
-    avg_kernel_s = region_ms * 1e-3 / args.steps
+    avg_kernel_s = region_ms * 1e-3 / steps  # one launch per step
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
-    achieved = bytes_per_launch / avg_kernel_s / 1e9
-    order_names = {0: "given", 1: "largest_first", 2: "interleaved"}
+    key = "batch_sweep_64 %s %s %d %d %d %s" % (args.storage, layout, b_rows, int(bool(b_nt)),
+                                               b_tile, order)
     out = {
         "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step, batched runs)",
-        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f32 (fp16 storage)",
-                  "bf16": "f32 (bf16 storage)"}[args.storage],
-        "data": "synthetic (lattice flows from a uniform inflow state; no dataset)",
+        "value": round(nodes * steps / (region_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(region_ms / steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.storage], "data": DATA,
         "config": {"workload": "batch_sweep_64", "runs": len(members), "nodes": nodes,
-                   "storage": args.storage, "graph_steps": args.graph_steps,
+                   "storage": args.storage, "layout": layout, "graph_steps": args.graph_steps,
                    "rows_per_tile": b_rows, "nontemporal_stores": bool(b_nt),
-                   "tile_width": b_tile,
-                   "order": order_names[tuned[2]] if tuned else "largest_first"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_step<%s> (batched)" % args.storage,
-                     "avg_kernel_us": round(avg_kernel_s * 1e6, 3),
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                   "tile_width": b_tile, "order": order, "autotuned": tuned is not None},
+        "roofline": roofline(args, bytes_per_launch, avg_kernel_s,
+                             "k_step<%s> (batched)" % args.storage, key),
         "wall_s": round(wall, 3),
     }
     if args.accuracy_steps:
         out["accuracy_vs_fp64"] = batch_accuracy(args, vplbm, W)
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline_batch(sweep, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(sweep, args.cpu_seconds, "64 runs of the sweep")
+    print(json.dumps(out), flush=True)
+
+
+SINGLE = {
+    "free_viv": ("free_viv_2048x1024", "disc D=40, free in y, mass ratio 10, U_r 5, Re 150"),
+    "sedimentation": ("sedimentation_1024x4096",
+                      "disc D=32, density ratio 1.5, free in x, y, theta; closed box, Re_p 1"),
+    "roofline": ("roofline_8192x8192", "fixed disc D=512, Re 100"),
+}
+
+
+def run_single(args):
+    import torch
+    from paper_1905_05110_amd import workloads as W
+    from paper_1905_05110_amd import vplbm
+
+    steps = args.steps or DEFAULT_STEPS[args.workload]
+    wl = {"free_viv": W.free_viv, "sedimentation": W.sedimentation,
+          "roofline": W.roofline_grid}[args.workload](storage=args.storage)
+    spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store,
+                tile_width=args.tile_width, layout=args.layout)
+    nodes = spec["nx"] * spec["ny"]
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = vplbm.Sim(spec, wl["body"], torch_memory=True, history_cap=1 << 16)
+        w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
+        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+        sim.step(w_pre)
+        sim.sync()
+        seeded_state(sim)
+        tuned = None
+        if not args.no_autotune and not pinned(args):
+            print("autotune", file=sys.stderr, flush=True)
+            tuned = sim.autotune(trial_steps=max(4, min(50, int(2e9 / nodes))))
+        rows, nt, tile = sim.launch_config()
+        if args.graph_steps:
+            sim.set_graph_steps(args.graph_steps)
+        sim.step(w_post)
+        sim.sync()
+        seeded_state(sim)
+        region_ms, wall = timed(stream, sim.step, steps)
+        sim.sync()
+        layout = sim.layout_name()
+    avg_kernel_s = region_ms * 1e-3 / steps  # one step-kernel launch per step
+    bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
+    name, body = SINGLE[args.workload]
+    key = "%s %s %s %d %d %d -" % (name, args.storage, layout, rows, int(bool(nt)), tile)
+    out = {
+        "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step)",
+        "value": round(nodes * steps / (region_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(region_ms / steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.storage], "data": DATA,
+        "config": {"workload": name, "nx": spec["nx"], "ny": spec["ny"], "storage": args.storage,
+                   "layout": layout, "body": body, "graph_steps": args.graph_steps,
+                   "rows_per_tile": rows, "nontemporal_stores": bool(nt), "tile_width": tile,
+                   "autotuned": tuned is not None},
+        "roofline": roofline(args, bytes_per_launch, avg_kernel_s, "k_step<%s>" % args.storage,
+                             key),
+        "wall_s": round(wall, 3),
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline([wl], args.cpu_seconds, "%s grid" % name)
     print(json.dumps(out), flush=True)
 
 
@@ -260,8 +391,8 @@ def cpu_baseline_adjoint(target_seconds):
     import torch
     from oracle import adjoint_oracle as ado
     from paper_1905_05110_amd import workloads as W
-    cores = min(len(os.sched_getaffinity(0)), 16)
-    torch.set_num_threads(cores)
+    model, avail = cpu_info()
+    torch.set_num_threads(min(avail, CPU_SHARE))
     wl = W.adjoint_drag(storage="fp64", nx=128, ny=64, D=8.0)
     m = ado.Mirror(wl["spec"], wl["body"])
     t0 = time.perf_counter()
@@ -273,7 +404,8 @@ def cpu_baseline_adjoint(target_seconds):
     dt = time.perf_counter() - t0
     return {"value": round(128 * 64 * n / dt / 1e6, 3), "unit": "MLUPS (forward + reverse)",
             "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": "reverse-mode oracle, 128x64 copy, %d steps (%.1f s)" % (n, dt)}
+            "sample": "reverse-mode oracle, 128x64 copy, %d steps (%.1f s)" % (n, dt),
+            "cpu_model": model, "cores_visible": avail, "cores_share": CPU_SHARE}
 
 
 def run_adjoint(args):
@@ -285,7 +417,8 @@ def run_adjoint(args):
     steps, every = wl["steps"], wl["checkpoint_every"]
     w = (1.0 / (steps * 0.5 * wl["U0"] ** 2 * wl["D"]), 0.0)
     nodes = wl["spec"]["nx"] * wl["spec"]["ny"]
-    adj = vplbm.Adjoint(wl["spec"], wl["body"], steps, every, w, graphs=args.graph_steps != 0)
+    spec = dict(wl["spec"], layout=args.layout)
+    adj = vplbm.Adjoint(spec, wl["body"], steps, every, w, graphs=args.graph_steps != 0)
     print("adjoint warm-up", file=sys.stderr, flush=True)
     J = adj.forward()
     adj.backward()
@@ -312,8 +445,7 @@ def run_adjoint(args):
         "metric": "adjoint/forward time ratio (gradient of time-averaged drag)",
         "value": round(bwd / fwd, 3), "unit": "ratio", "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": round(1e3 * (fwd + bwd) / steps, 5), "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64"}[args.storage],
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.storage],
         "data": "synthetic (channel flow from a uniform inflow state; no dataset)",
         "config": {"workload": "adjoint_drag_1024x512", "nx": wl["spec"]["nx"],
                    "ny": wl["spec"]["ny"], "storage": args.storage, "D": wl["D"], "Re": 100,
@@ -349,86 +481,7 @@ def main():
             print("the adjoint runs in fp32 or fp64 storage", file=sys.stderr)
             sys.exit(2)
         return run_adjoint(args)
-    import torch
-    from paper_1905_05110_amd import workloads as W
-    from paper_1905_05110_amd import vplbm
-
-    wl = W.free_viv(storage=args.storage)
-    spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store,
-                tile_width=args.tile_width)
-    body = wl["body"]
-    nodes = spec["nx"] * spec["ny"]
-    if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        sim = vplbm.Sim(spec, body, torch_memory=True, history_cap=1 << 17)
-        tuned = None
-        w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
-        print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-        sim.step(w_pre)
-        sim.sync()
-        if not args.no_autotune and args.rows == 0 and args.store == "auto" and not args.tile_width:
-            print("autotune", file=sys.stderr, flush=True)
-            tuned = sim.autotune(trial_steps=50)
-        rows, nt, tile = sim.launch_config()
-        if args.graph_steps:
-            sim.set_graph_steps(args.graph_steps)
-        sim.step(w_post)
-        sim.sync()
-        torch.cuda.synchronize()
-        # timed region: K full steps on the simulation's stream, bracketed by events
-        print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        sim.step(args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        region_ms = e0.elapsed_time(e1)
-        sim.sync()
-    ms_per_step = region_ms / args.steps
-    mlups = nodes * args.steps / (region_ms * 1e-3) / 1e6
-    avg_kernel_s = region_ms * 1e-3 / args.steps  # one step-kernel launch per step
-    bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
-    achieved = bytes_per_launch / avg_kernel_s / 1e9
-    out = {
-        "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step)",
-        "value": round(mlups, 1),
-        "unit": "MLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f32 (fp16 storage)",
-                  "bf16": "f32 (bf16 storage)"}[args.storage],
-        "data": "synthetic (lattice flow from a uniform inflow state; no dataset)",
-        "config": {"workload": "free_viv_2048x1024", "nx": spec["nx"], "ny": spec["ny"],
-                   "storage": args.storage, "body": "disc D=40, free in y, mass ratio 10, U_r 5",
-                   "Re": 150, "graph_steps": args.graph_steps,
-                   "rows_per_tile": rows, "nontemporal_stores": bool(nt), "tile_width": tile},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_for(args.traffic, args.storage, spec["nx"], spec["ny"],
-                                            rows, nt, tile),
-                     "kernel": "k_step<%s>" % args.storage,
-                     "avg_kernel_us": round(avg_kernel_s * 1e6, 3),
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
-        "wall_s": round(wall, 3),
-    }
-    if not args.no_cpu_baseline:
-        print("cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
-    sim.close()
+    return run_single(args)
 
 
 if __name__ == "__main__":

@@ -65,13 +65,27 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
 
 /* Reference equilibrium of the stored offsets: INITIAL uses f_eq(1, u0) (the initial
  * or inflow state, so a uniform stream is stored as zeros); REST uses the rest-state
- * weights w_a = f_eq(1, 0). */
-enum { LBM_REF_INITIAL = 0, LBM_REF_REST = 1 };
+ * weights w_a = f_eq(1, 0); AUTO (the default) takes REST for the 16-bit storages and
+ * INITIAL for FP32 and FP64.  With 16-bit storage the rest reference keeps the stored
+ * magnitudes, hence the rounding, smallest where the flow is slow (near the body). */
+enum { LBM_REF_AUTO = 0, LBM_REF_INITIAL = 1, LBM_REF_REST = 2 };
 
 /* Store instructions for the populations: PLAIN keeps them in the caches (a grid whose
  * two buffers fit the 256 MB Infinity Cache then runs from it); NONTEMPORAL streams
  * them past the caches; AUTO picks NONTEMPORAL above 1 GiB of buffers. */
 enum { LBM_STORE_AUTO = 0, LBM_STORE_PLAIN = 1, LBM_STORE_NONTEMPORAL = 2 };
+
+/* Arrangement of the nine population arrays of a buffer (each row of a direction holds
+ * pitch = nx rounded up to 64 elements):
+ *   ROWS    row-interleaved: row j of direction a at element (9 j + a) pitch, so that the
+ *           three source rows and the destination row of a node lie close together;
+ *   PLANES  one plane per direction, [9][ny][pitch] plus a small pad between planes;
+ *   AUTO    ROWS when the whole buffer is below 4 GiB (population addresses are 32-bit
+ *           byte offsets from a direction's base), else PLANES.
+ * PLANES needs each plane below 4 GiB (about 1.07 G nodes in FP32, 537 M in FP64);
+ * lbm_create refuses larger grids with LBM_ERR_ARG.  Both take lbm_pop_bytes() bytes;
+ * results are bitwise the same in either. */
+enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_ROWS = 1, LBM_LAYOUT_PLANES = 2 };
 
 /* Collision operator.  MRT relaxes the moments of Eq. (9) at the rates of lbm_rates
  * (Eqs. (8), (16)); BGK (Sec. 2.2, Eqs. (11)-(12) with Guo's source) relaxes every
@@ -125,7 +139,7 @@ typedef struct {
     int storage;           /* LBM_FP64 / LBM_FP32 / LBM_FP16_OFS / LBM_BF16_OFS */
     int fp16_scale_log2;   /* k of the FP16 offset scale 2^k, 0..14 (default 10) */
     int history_cap;       /* force records kept on the device between drains (default 65536) */
-    int offset_ref;        /* LBM_REF_INITIAL (default) or LBM_REF_REST */
+    int offset_ref;        /* LBM_REF_AUTO (default), LBM_REF_INITIAL or LBM_REF_REST */
     int rows_per_tile;     /* grid rows per tile (nodes per lane): 1, 2, 4;
                               0 = default (1).  Each setting is deterministic; results of
                               different settings agree to rounding (kernel variants may
@@ -139,6 +153,7 @@ typedef struct {
                               kernel): 0 = default (256), 256 or 512.  Like rows_per_tile
                               a launch choice: results of different settings agree to
                               rounding (the FP64 force sums follow the tile order). */
+    int layout;            /* LBM_LAYOUT_AUTO (default), _ROWS or _PLANES */
 } lbm_opts;
 
 typedef struct {
@@ -259,6 +274,9 @@ int lbm_autotune(lbm_sim* sim, int trial_steps, const char* cache_path, int* row
  * Outputs may be NULL. */
 int lbm_launch_config(const lbm_sim* sim, int* rows_out, int* nt_out, int* tile_width_out);
 
+/* The population layout in use: LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES (never AUTO). */
+int lbm_layout(const lbm_sim* sim, int* layout_out);
+
 /* Serialises the full state (populations, outflow memory, body, step index) into a
  * host buffer; with buf NULL only *size_out is set.  lbm_load restores a state saved
  * from a simulation of the same grid and storage. */
@@ -293,6 +311,8 @@ typedef struct {
     int order;          /* LBM_ORDER_* */
     void* hip_stream;   /* NULL: the library creates one */
     int tile_width;     /* 0 (default: 256), 256 or 512 */
+    int layout;         /* LBM_LAYOUT_AUTO: each member's own opts->layout; else every
+                           member takes this one */
 } lbm_batch_opts;
 
 void lbm_default_batch_opts(lbm_batch_opts* o);
@@ -327,6 +347,9 @@ int lbm_batch_configure(lbm_batch* batch, int rows, int store_mode, int order);
  * Outputs may be NULL; us_out is the time per batch step in microseconds. */
 int lbm_batch_autotune(lbm_batch* batch, int trial_steps, int* rows_out, int* nt_out,
                        int* order_out, double* us_out);
+
+/* The schedule order in use (LBM_ORDER_*). */
+int lbm_batch_order(const lbm_batch* batch, int* order_out);
 
 int lbm_batch_destroy(lbm_batch* batch);
 const char* lbm_batch_last_error(const lbm_batch* batch);

@@ -380,7 +380,7 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     A->out_bytes = 3 * (size_t)ny * A->tsz;
     A->atx = (nx + TILE_X - 1) / TILE_X;
     const size_t pb = s->pop_bytes, ob = A->out_bytes;
-    const size_t plane_b = (size_t)s->desc.ps * A->tsz;
+    const size_t plane_b = (size_t)s->desc.fpitch * ny * A->tsz;  // dJ/dchi, [ny][fpitch]
     auto alloc = [&](void** p, size_t bytes) {
         hipError_t e = hipMalloc(p, bytes);
         if (e != hipSuccess) A->err = std::string("hipMalloc: ") + hipGetErrorString(e);
@@ -573,7 +573,7 @@ int lbm_adjoint_backward(lbm_adjoint* A) {
     lbm_sim* s = A->sim;
     A->bwd_done = false;
     int rc = zero_words(A, A->abar[(A->steps) & 1], s->pop_bytes);
-    if (!rc) rc = zero_words(A, A->chibar, (size_t)s->desc.ps * A->tsz);
+    if (!rc) rc = zero_words(A, A->chibar, (size_t)s->desc.fpitch * s->ny * A->tsz);
     if (!rc) rc = zero_words(A, A->tile_acc, (size_t)A->atx * A->ny * 3 * sizeof(double));
     if (rc) return rc;
     const int last = A->nseg - 1;

@@ -148,11 +148,16 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
         return m = "collision must be LBM_COLLIDE_MRT or LBM_COLLIDE_BGK", LBM_ERR_ARG;
     if (o.store_mode < LBM_STORE_AUTO || o.store_mode > LBM_STORE_NONTEMPORAL)
         return m = "unknown store mode", LBM_ERR_ARG;
-    if (o.offset_ref != LBM_REF_INITIAL && o.offset_ref != LBM_REF_REST)
+    if (o.offset_ref != LBM_REF_AUTO && o.offset_ref != LBM_REF_INITIAL && o.offset_ref != LBM_REF_REST)
         return m = "unknown offset reference", LBM_ERR_ARG;
     if (!(o.rho0 > 0.0)) return m = "rho0 must be > 0", LBM_ERR_ARG;
     if ((o.pop_buffers[0] == nullptr) != (o.pop_buffers[1] == nullptr))
         return m = "pass both population buffers or neither", LBM_ERR_ARG;
+    if (o.layout < LBM_LAYOUT_AUTO || o.layout > LBM_LAYOUT_PLANES)
+        return m = "unknown layout", LBM_ERR_ARG;
+    int pitch, layout;
+    long long ps;
+    if (!pop_geometry(nx, ny, o.storage, o.layout, pitch, ps, layout, m)) return LBM_ERR_ARG;
     return LBM_OK;
 }
 
@@ -252,10 +257,13 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.part_stride = (long long)ntiles * NRED;
     d.hist = s->hist;
     d.flag = s->flag;
-    d.ps = plane_stride(nx, ny);
+    {
+        std::string m;
+        (void)pop_geometry(nx, ny, o.storage, o.layout, d.pitch, d.ps, d.layout, m);  // checked above
+    }
+    d.fpitch = row_pitch(nx);
     d.nx = nx;
     d.ny = ny;
-    d.pitch = row_pitch(nx);
     d.rows = s->rows;
     d.tiles_x = tiles_x;
     d.tile_w = tile_w;
@@ -263,7 +271,9 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.hist_cap = s->hist_cap;
     for (int k = 0; k < 4; ++k) d.bc[k] = o.bc[k];
     // reference state of the stored offsets
-    const bool ref_rest = o.offset_ref == LBM_REF_REST;
+    const bool ref_rest = o.offset_ref == LBM_REF_REST ||
+                          (o.offset_ref == LBM_REF_AUTO &&
+                           (o.storage == LBM_FP16_OFS || o.storage == LBM_BF16_OFS));
     d.u0x = ref_rest ? 0.0 : o.u0[0];
     d.u0y = ref_rest ? 0.0 : o.u0[1];
     equilibrium(1.0, d.u0x, d.u0y, d.fref);
@@ -832,10 +842,16 @@ int lbm_launch_config(const lbm_sim* s, int* rows_out, int* nt_out, int* tile_wi
     return LBM_OK;
 }
 
+int lbm_layout(const lbm_sim* s, int* layout_out) {
+    if (!s || !layout_out) return LBM_ERR_ARG;
+    *layout_out = s->desc.layout;
+    return LBM_OK;
+}
+
 // ---- save / load -------------------------------------------------------------------
 struct SaveHeader {
     char magic[8];
-    int version, nx, ny, storage;
+    int version, nx, ny, storage, layout;
     long long host_step, drained;
     unsigned long long pop_bytes, outlet_bytes;
 };
@@ -853,10 +869,11 @@ int lbm_save(lbm_sim* s, void* buf, size_t cap, size_t* size_out) {
     SaveHeader h;
     std::memset(&h, 0, sizeof(h));
     std::memcpy(h.magic, "VPLBMS1", 8);
-    h.version = 1;
+    h.version = 2;
     h.nx = s->nx;
     h.ny = s->ny;
     h.storage = s->storage;
+    h.layout = s->desc.layout;
     h.host_step = s->host_step;
     h.drained = s->drained;
     h.pop_bytes = s->pop_bytes;
@@ -880,8 +897,9 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     std::memcpy(&h, buf, sizeof(h));
     const size_t tsz = s->storage == LBM_FP64 ? 8 : 4;
     const size_t ob = 3 * (size_t)s->ny * tsz;
-    if (std::memcmp(h.magic, "VPLBMS1", 8) != 0 || h.version != 1 || h.nx != s->nx ||
-        h.ny != s->ny || h.storage != s->storage || h.pop_bytes != s->pop_bytes ||
+    if (std::memcmp(h.magic, "VPLBMS1", 8) != 0 || h.version != 2 || h.nx != s->nx ||
+        h.ny != s->ny || h.storage != s->storage || h.layout != s->desc.layout ||
+        h.pop_bytes != s->pop_bytes ||
         h.outlet_bytes != ob || size < sizeof(h) + s->pop_bytes + ob + sizeof(BodyDev))
         return fail(s, LBM_ERR_ARG, "saved state does not match this simulation");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -1070,6 +1088,8 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
         return g_batch_create_error = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
     if (bo.tile_width != 0 && bo.tile_width != TILE_X && bo.tile_width != TILE_WIDE)
         return g_batch_create_error = "tile_width must be 0, 256 or 512", LBM_ERR_ARG;
+    if (bo.layout < LBM_LAYOUT_AUTO || bo.layout > LBM_LAYOUT_PLANES)
+        return g_batch_create_error = "unknown layout", LBM_ERR_ARG;
     lbm_batch* b = new lbm_batch();
     b->n = n;
     b->storage = bo.storage;
@@ -1103,6 +1123,7 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
         o.rows_per_tile = bo.rows_per_tile;
         o.store_mode = bo.store_mode;
         o.tile_width = bo.tile_width;
+        if (bo.layout != LBM_LAYOUT_AUTO) o.layout = bo.layout;
         b->in_opts[i] = o;
         if (descs[i].body) {
             b->in_body[i] = *descs[i].body;
@@ -1137,6 +1158,12 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
     int rc = batch_upload(b);
     if (rc) return bail(rc);
     *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_order(const lbm_batch* b, int* order_out) {
+    if (!b || !order_out) return LBM_ERR_ARG;
+    *order_out = b->order;
     return LBM_OK;
 }
 

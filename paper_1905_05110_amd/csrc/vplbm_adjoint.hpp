@@ -42,7 +42,7 @@ struct RingEntry {
 };
 
 // One reader of an edge population in the transposed pull, as the kernel reads it: the
-// element index (plane a, then j * pitch + i) of the reader's adjoint value and the
+// element index (a * ps + j * pitch + i) of the reader's adjoint value and the
 // weight of the read.  Unused slots have weight 0 and index 0.
 struct RingSlot {
     long long idx;
@@ -57,7 +57,7 @@ struct AdjDesc {
     const char* ckpt_pop;   // one checkpoint per segment (state at the segment start)
     const char* ckpt_out;
     void* abar[2];          // Pbar of the two parities, 9 planes of ps values
-    void* chibar;           // dJ/dchi accumulated over the steps, [ny][pitch]
+    void* chibar;           // dJ/dchi accumulated over the steps, [ny][fpitch]
     double* tile_acc;       // per tile of the adjoint grid: u_s adjoint sums (x, y, angular)
     const RingSlot* ring;   // ring_k readers per (edge node, direction)
     const int* ring_kn;     // per edge node: the slots it visits (its longest list)
@@ -123,7 +123,7 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         T w[NQ];
         const unsigned row = (unsigned)d.pitch;
         const unsigned o0 = (unsigned)j * row + (unsigned)i;
-        T* chib = reinterpret_cast<T*>(a.chibar) + o0;
+        T* chib = reinterpret_cast<T*>(a.chibar) + ((long long)j * d.fpitch + i);
         const T chib_old = gld(chib);
         if (inner) {
 #pragma unroll
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(TILE_X) void k_adj_reduce(const SimDesc* __restrict
         const int i = a.nbox[0] + (int)(k % bw), j = a.nbox[2] + (int)(k / bw);
         double dX, dY;
         chi_pose_derivative(B, (double)i - a.pose[0], (double)j - a.pose[1], dX, dY);
-        const double cb = (double)chib[(long long)j * d.pitch + i];
+        const double cb = (double)chib[(long long)j * d.fpitch + i];
         t[0] += cb * dX;
         t[1] += cb * dY;
     }
@@ -355,7 +355,7 @@ __global__ void k_adj_export(const SimDesc* __restrict__ dp, const AdjDesc* __re
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     out[(long long)j * d.nx + i] =
-        (double)reinterpret_cast<const S*>(ap->chibar)[(long long)j * d.pitch + i];
+        (double)reinterpret_cast<const S*>(ap->chibar)[(long long)j * d.fpitch + i];
 }
 
 // Launch interface, instantiated for S = double and float in adj_<storage>.hip.

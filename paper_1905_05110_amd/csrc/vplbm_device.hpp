@@ -126,8 +126,12 @@ struct SimDesc {
     long long part_stride;  // doubles per parity in partials
     Record* hist;        // ring of per-step records
     int* flag;           // set to 1 when an unstable node is met
-    long long ps;        // plane stride (elements)
-    int nx, ny, pitch, rows, tiles_x, tiles_y, hist_cap;
+    long long ps;        // stride between the population arrays of two directions (elements)
+    int nx, ny;
+    int pitch;           // stride between two rows of one direction's populations (elements)
+    int fpitch;          // row stride of a single-field array such as dJ/dchi (elements)
+    int layout;          // LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES (pitch and ps follow from it)
+    int rows, tiles_x, tiles_y, hist_cap;
     int tile_w;          // columns per tile of the step kernel: TILE_X or TILE_WIDE
     int bc[4];
     // x-edge rule (west, east) for the three directions whose source lies outside (1, 5, 8
@@ -618,6 +622,22 @@ __device__ __forceinline__ void macros(const C& c, const T g[NQ], T chi, T dsx, 
     o.jgy = jgy;
 }
 
+// x / k for a small integer k, from the rounded reciprocal inv_k = RN(1/k).  The product
+// x * inv_k alone carries the constant's own rounding, the same relative error at every
+// node and step (RN(1/6) and RN(1/9) both lie above the true values in FP32); dividing
+// the conserved moments that way adds momentum and mass coherently, step after step.
+// One correction step from the exact residual x - k q (a single FMA: k q is within an
+// ulp of x) gives the correctly rounded quotient, whose error is no longer biased.
+template <class T>
+__device__ __forceinline__ T div_small(T x, T k, T inv_k) {
+    const T q = x * inv_k;
+    return __builtin_fma(__builtin_fma(-k, q, x), inv_k, q);
+}
+__device__ __forceinline__ float div_small(float x, float k, float inv_k) {
+    const float q = x * inv_k;
+    return __builtin_fmaf(__builtin_fmaf(-k, q, x), inv_k, q);
+}
+
 // Collision in moment space with the forcing source (Eqs. (8), (14), (16), (17); the
 // source enters with the sign of Eq. (8)):  m* = m - S (m - m_eq) + (I - S/2) M F,
 // F the Guo forcing vector of Eq. (12) without its (1 - 1/2tau) factor, whose moments
@@ -664,13 +684,15 @@ __device__ __forceinline__ void collide(const C& c, const T g[NQ], T chi, T dsx,
     const T jx_s = o.jgx + Gx;
     const T jy_s = o.jgy + Gy;
 
-    // f = M^-1 m*, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-    const T a0 = drho * T(1.0 / 9.0);
+    // f = M^-1 m*, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+    // The mass and momentum of the result are 9 a0 and 6 (a3, a5) exactly, so those three
+    // quotients are correctly rounded (div_small); the others relax.
+    const T a0 = div_small(drho, T(9), T(1.0 / 9.0));
     const T a1 = e_s * T(1.0 / 36.0);
     const T a2 = ep_s * T(1.0 / 36.0);
-    const T a3 = jx_s * T(1.0 / 6.0);
+    const T a3 = div_small(jx_s, T(6), T(1.0 / 6.0));
     const T a4 = qx_s * T(1.0 / 12.0);
-    const T a5 = jy_s * T(1.0 / 6.0);
+    const T a5 = div_small(jy_s, T(6), T(1.0 / 6.0));
     const T a6 = qy_s * T(1.0 / 12.0);
     const T a7 = pxx_s * T(0.25);
     const T a8 = pxy_s * T(0.25);

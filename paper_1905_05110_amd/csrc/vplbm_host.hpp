@@ -27,6 +27,34 @@ inline long long plane_stride(int nx, int ny) {
     return (long long)row_pitch(nx) * ny + 320;
 }
 
+// Strides of the population arrays of one buffer (elements): between the rows of one
+// direction (SimDesc::pitch) and between directions (SimDesc::ps).  ROWS puts row j of
+// direction a at (9 j + a) row_pitch: the rows a node's pull reads and the row it writes
+// then lie within a few row lengths of each other, which the memory system serves
+// faster than nine separate planes.  Kernels address populations with 32-bit byte
+// offsets from a direction's base, so ROWS needs the whole buffer, PLANES one plane,
+// below 4 GiB; returns false (with a message) when the request does not fit.
+inline bool pop_geometry(int nx, int ny, int storage, int request, int& pitch, long long& ps,
+                         int& layout, std::string& msg) {
+    const long long rp = row_pitch(nx);
+    const long long e = (long long)elem_size(storage);
+    const long long lim = 1LL << 32;
+    const bool rows_fit = (long long)NQ * rp * ny * e < lim;
+    const bool planes_fit = plane_stride(nx, ny) * e < lim;
+    if (request == LBM_LAYOUT_ROWS || (request == LBM_LAYOUT_AUTO && rows_fit)) {
+        if (!rows_fit) return msg = "grid too large for the ROWS layout (buffer of 4 GiB or more)", false;
+        pitch = (int)(NQ * rp);
+        ps = rp;
+        layout = LBM_LAYOUT_ROWS;
+        return true;
+    }
+    if (!planes_fit) return msg = "grid too large: a population plane reaches 4 GiB", false;
+    pitch = (int)rp;
+    ps = plane_stride(nx, ny);
+    layout = LBM_LAYOUT_PLANES;
+    return true;
+}
+
 }  // namespace vplbm
 
 using vplbm::BodyDev;

@@ -22,16 +22,18 @@ MODE = {"fixed": 0, "imposed_sin": 1, "free": 2, "const_vel": 3}
 FORCE = {"vp": 0, "mem": 1, "vp+mem": 2}  # driving load; "mem"/"vp+mem" evaluate the exchange sum
 STORE = {"auto": 0, "plain": 1, "nontemporal": 2}
 ORDER = {"given": 0, "largest_first": 1, "interleaved": 2}
+OFFSET_REF = {"auto": 0, "initial": 1, "rest": 2}  # auto: rest for 16-bit storage, else initial
+LAYOUT = {"auto": 0, "rows": 1, "planes": 2}
 
 EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
            "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
            "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
-           "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_launch_config",
+           "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_launch_config", "lbm_layout",
            "lbm_save", "lbm_load",
            "lbm_destroy", "lbm_last_error",
            "lbm_default_batch_opts", "lbm_batch_create", "lbm_batch_step",
            "lbm_batch_set_graph_steps", "lbm_batch_sync", "lbm_batch_sim", "lbm_batch_size",
-           "lbm_batch_configure", "lbm_batch_autotune", "lbm_batch_destroy",
+           "lbm_batch_configure", "lbm_batch_autotune", "lbm_batch_order", "lbm_batch_destroy",
            "lbm_batch_last_error",
            "lbm_default_adjoint_opts", "lbm_adjoint_create", "lbm_adjoint_set_body",
            "lbm_adjoint_set_initial", "lbm_adjoint_forward", "lbm_adjoint_forces",
@@ -56,7 +58,8 @@ class Opts(C.Structure):
                 ("storage", C.c_int), ("fp16_scale_log2", C.c_int), ("history_cap", C.c_int),
                 ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
                 ("hip_stream", C.c_void_p),
-                ("pop_buffers", C.c_void_p * 2), ("collision", C.c_int), ("tile_width", C.c_int)]
+                ("pop_buffers", C.c_void_p * 2), ("collision", C.c_int), ("tile_width", C.c_int),
+                ("layout", C.c_int)]
 
 
 class Body(C.Structure):
@@ -77,7 +80,8 @@ class BatchDesc(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("storage", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
-                ("order", C.c_int), ("hip_stream", C.c_void_p), ("tile_width", C.c_int)]
+                ("order", C.c_int), ("hip_stream", C.c_void_p), ("tile_width", C.c_int),
+                ("layout", C.c_int)]
 
 
 class AdjointOpts(C.Structure):
@@ -124,6 +128,7 @@ def load_library(path=LIB_PATH):
     L.lbm_autotune.argtypes = [P, C.c_int, C.c_char_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_double)]
     L.lbm_launch_config.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.lbm_layout.argtypes = [P, C.POINTER(C.c_int)]
     L.lbm_save.argtypes = [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbm_load.argtypes = [P, C.c_void_p, C.c_size_t]
     L.lbm_destroy.argtypes = [P]
@@ -141,6 +146,7 @@ def load_library(path=LIB_PATH):
     L.lbm_batch_configure.argtypes = [P, C.c_int, C.c_int, C.c_int]
     L.lbm_batch_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.lbm_batch_order.argtypes = [P, C.POINTER(C.c_int)]
     L.lbm_batch_destroy.argtypes = [P]
     L.lbm_batch_last_error.argtypes = [P]
     L.lbm_batch_last_error.restype = C.c_char_p
@@ -186,11 +192,12 @@ def make_opts(spec, stream=None, buffers=None, history_cap=65536):
     o.storage = STORAGE[st] if isinstance(st, str) else int(st)
     o.fp16_scale_log2 = int(spec.get("fp16_scale_log2", 10))
     o.history_cap = int(history_cap)
-    o.offset_ref = {"initial": 0, "rest": 1}[spec.get("offset_ref", "initial")]
+    o.offset_ref = OFFSET_REF[spec.get("offset_ref", "auto")]
     o.rows_per_tile = int(spec.get("rows_per_tile", 0))
     o.store_mode = {"auto": 0, "plain": 1, "nontemporal": 2}[spec.get("store_mode", "auto")]
     o.collision = {"mrt": 0, "bgk": 1}[spec.get("collision", "mrt")]
     o.tile_width = int(spec.get("tile_width", 0))
+    o.layout = LAYOUT[spec.get("layout", "auto")]
     o.hip_stream = stream
     if buffers is not None:
         o.pop_buffers[0], o.pop_buffers[1] = buffers
@@ -343,6 +350,12 @@ class Sim:
         self._check(self.L.lbm_launch_config(self.h, C.byref(r), C.byref(n), C.byref(w)))
         return r.value, n.value, w.value
 
+    def layout_name(self):
+        """The population layout in use: "rows" or "planes"."""
+        v = C.c_int()
+        self._check(self.L.lbm_layout(self.h, C.byref(v)))
+        return {LAYOUT["rows"]: "rows", LAYOUT["planes"]: "planes"}[v.value]
+
     def save(self):
         size = C.c_size_t()
         self._check(self.L.lbm_save(self.h, None, 0, C.byref(size)))
@@ -383,7 +396,7 @@ class Batch:
     """
 
     def __init__(self, members, storage="fp32", order="largest_first", rows=0, store="auto",
-                 history_cap=65536, graph_steps=0, stream=None, tile_width=0):
+                 history_cap=65536, graph_steps=0, stream=None, tile_width=0, layout="auto"):
         L = load_library()
         self.L = L
         self.h = None
@@ -408,6 +421,7 @@ class Batch:
         bo.store_mode = STORE[store] if isinstance(store, str) else int(store)
         bo.hip_stream = stream
         bo.tile_width = int(tile_width)
+        bo.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)
         h = C.c_void_p()
         rc = L.lbm_batch_create(n, descs, C.byref(bo), C.byref(h))
         if rc != LBM_OK:
@@ -450,6 +464,12 @@ class Batch:
         self._check(self.L.lbm_batch_autotune(self.h, int(trial_steps), C.byref(r), C.byref(n),
                                               C.byref(o), C.byref(us)))
         return r.value, n.value, o.value, us.value
+
+    def order_name(self):
+        """The schedule order in use."""
+        v = C.c_int()
+        self._check(self.L.lbm_batch_order(self.h, C.byref(v)))
+        return {k: n for n, k in ORDER.items()}[v.value]
 
     def close(self):
         if getattr(self, "h", None):

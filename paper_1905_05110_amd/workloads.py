@@ -144,7 +144,7 @@ def paper_sedimentation_centered(rho_ratio, storage="fp64", D=24.0, Ht=5.0, L=12
     closed (the net flux through every section is zero, as with the zero-velocity top
     and far outlet of the paper).  The disc is free in x, y and theta with
     m = rho_s pi D^2 / 4, I = m R^2 / 2 and the load of Eq. (31): m (1 - rho/rho_s) g.
-    Returns also the confined settling velocity of Eqs. (32)-(34) in lattice units."""
+    Returns also the confined settling velocity of Eqs. (33)-(35) in lattice units."""
     H = int(round(Ht * D))
     nu_l = (tau - 0.5) / 3.0
     dx = D_cm / D

@@ -6,7 +6,7 @@ against the values the paper prints or the closed form it compares with.
   momentum-exchange force.  Reading: the flow past the fixed disc is first run to
   periodic shedding (100 000 steps, t* = 119), then the motion starts; the mean is
   taken over the whole periods up to t* = 64 (the time of the paper's field snapshots).
-* Centred settling (Sec. 3.2.1, Eqs. (32)-(34)): H/D = 5, D = 24, tau = 0.8, six density
+* Centred settling (Sec. 3.2.1, Eqs. (33)-(35)): H/D = 5, D = 24, tau = 0.8, six density
   ratios; the terminal velocity against the confined Stokes settling velocity.  The
   paper finds agreement for rho_r in {0.98, 0.99, 1.01, 1.02} and a visible gap for
   0.95 and 1.05 (Re = 3.2, beyond the Stokes regime of the closed form).
@@ -121,9 +121,12 @@ def _response(y, y0, D, U0):
 def test_paper_viv_effective_stiffness(gpu):
     """Sec. 3.3: the paper prints k*_eff = k* - m* omega*^2 for k* = 9, 19, 28 (0.058,
     3.20, 16.37) and finds lock-in displacements above half a diameter.  m* is not
-    stated; with m* = 9 (from the k* = 28 case, whose response sits at the shedding
-    frequency) the lock-in case k* = 9 is predicted.  At k* = 19, on the edge of lock-in,
-    k*_eff moves by 1 for a 3 % change of the response frequency: bound 1.5 there."""
+    stated.  The k* = 28 case (response at the wake's shedding frequency) is the
+    calibration point: m* = 9 was chosen so that it reproduces 16.37, so its bound below
+    only confirms that calibration and is not a check of the method.  The checks are
+    the other two cases, predicted with that m*: the lock-in case k* = 9, and k* = 19 on
+    the edge of lock-in, where k*_eff moves by 1 for a 3 % change of the response
+    frequency (bound 1.5 there)."""
     wls = [W.paper_viv(k, storage="fp32") for k in (9.0, 19.0, 28.0)]
     _flush("paper VIV 1230x410, k* = 9, 19, 28 in one batch, 240000 steps")
     b = gpu.Batch([(w["spec"], w["body"]) for w in wls], storage="fp32", graph_steps=64)
@@ -140,8 +143,8 @@ def test_paper_viv_effective_stiffness(gpu):
         res[w["k_star"]] = (amp, keff)
         _flush("k* %g: amplitude %.3f D, omega* %.4f, k*_eff %.3f" % (w["k_star"], amp, om, keff))
     assert abs(res[9.0][1] - 0.058) <= 0.15
-    assert abs(res[28.0][1] - 16.37) <= 0.3
     assert abs(res[19.0][1] - 3.20) <= 1.5
+    assert abs(res[28.0][1] - 16.37) <= 0.3  # the calibration point of m* (not a check)
     assert max(res[9.0][0], res[19.0][0]) > 0.5  # lock-in: more than half a diameter
     assert res[28.0][0] < 0.1  # far from lock-in the displacement stays small
 

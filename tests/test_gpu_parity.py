@@ -122,8 +122,11 @@ def run_pair(gpu, spec, body, steps, seed, check_every=1, tol=1e-12, init_random
         else:
             assert not rg["fmem"].any() and not rg["tmem"].any()
         for key in keys:
+            # the hydrodynamic load and the exchange sums are differences of larger terms
+            # (internal momentum, link pairs): their round-off is held to 10 tol
+            ktol = tol * 10 if key in ("fh", "th", "fmem", "tmem") else tol
             if np.abs(ro[key]).max() > 1e-14:
-                assert fe[key] <= tol * 10, (s, key, fe)
+                assert fe[key] <= ktol, (s, key, fe)
         assert fe["q"] <= 1e-12 * max(nx, ny) and fe["v"] <= 1e-12, (s, fe)
     g.close()
     return worst
@@ -173,7 +176,7 @@ def test_tiny_grids_step_by_step_reduced(gpu, storage, bcname, bodykind):
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16", "fp32"])
 @pytest.mark.parametrize("bcname", ["channel", "periodic", "wallbox"])
-@pytest.mark.parametrize("rows,tile", [(1, 256), (2, 256), (1, 512), (2, 512)])
+@pytest.mark.parametrize("rows,tile", [(1, 256), (2, 256), (1, 512), (2, 512), (4, 256), (4, 512)])
 def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows, tile):
     """601 x 40 (three 256-column tiles or two 512-column ones, the last ragged and of odd
     width), free body across the first 256-column border: one step at a time from the
@@ -202,33 +205,40 @@ def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows, 
 
 
 @pytest.mark.parametrize("bcname", list(BCS))
-@pytest.mark.parametrize("nx,ny,rows,tile", [(130, 12, 1, 256), (130, 12, 2, 256), (600, 9, 2, 256),
-                                             (600, 9, 1, 512), (1100, 7, 2, 512)])
-def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows, tile):
+@pytest.mark.parametrize("nx,ny,rows,tile,layout", [
+    (130, 12, 1, 256, "rows"), (130, 12, 2, 256, "rows"), (600, 9, 2, 256, "rows"),
+    (600, 9, 1, 512, "rows"), (1100, 7, 2, 512, "rows"), (130, 12, 4, 256, "rows"),
+    (600, 9, 4, 512, "rows"), (1100, 7, 4, 256, "rows"),
+    (130, 12, 1, 256, "planes"), (600, 9, 4, 512, "planes")])
+def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows, tile, layout):
     """Grids wider than a wave: the waves holding the west or the east node of an
     interior row take the x-edge pull (the east node at 129 sits in a partly filled
-    wave), the first and last rows the general one; every boundary set, rows per tile 1
-    and 2 (the second row's pull comes after the first row's stores), a body near the
+    wave), the first and last rows the general one; every boundary set, rows per tile 1,
+    2 and 4 (the later rows' pulls come after the earlier rows' stores; 9 and 7 rows
+    leave a partly filled last tile row), both population layouts, a body near the
     west edge."""
-    _flush("x-edge %s %dx%d rows %d tile %d" % (bcname, nx, ny, rows, tile))
+    _flush("x-edge %s %dx%d rows %d tile %d %s" % (bcname, nx, ny, rows, tile, layout))
     spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04,
                    g=(2e-5, -1e-5) if bcname in ("periodic", "pipe") else (0.0, 0.0))
     spec["rows_per_tile"] = rows
     spec["tile_width"] = tile
+    spec["layout"] = layout
     b = W.fixed_disc(5.0, 4.3, ny / 2.0 - 0.3)
     b.update(vx=0.002, omega=0.001, force_model="vp+mem")
     run_pair(gpu, spec, b, steps=6, seed=7)
 
 
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
-@pytest.mark.parametrize("tile,xb", [(256, 256.3), (512, 511.7)])
-def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb):
+@pytest.mark.parametrize("tile,xb,rows", [(256, 256.3, 1), (512, 511.7, 1), (256, 256.3, 4),
+                                          (512, 511.7, 4)])
+def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb, rows):
     """nx = 600 spans three 256-wide tiles or two 512-wide ones, the last one ragged;
-    the body straddles a tile border."""
+    the body straddles a tile border; one or four rows per tile."""
     nx, ny = 600, 24
-    _flush("ragged %s tile %d" % (bcname, tile))
+    _flush("ragged %s tile %d rows %d" % (bcname, tile, rows))
     spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04)
     spec["tile_width"] = tile
+    spec["rows_per_tile"] = rows
     b = W.fixed_disc(14.0, xb, 11.6)
     b.update(mode="free", free_mask=7, mass=300.0, inertia=2000.0, k=(0.01, 0.01, 0.0),
              q0=(xb, 11.6, 0.0))
@@ -301,17 +311,18 @@ def test_imposed_oscillation_full_run_fp64(gpu):
 
 def test_imposed_oscillation_fp32_velocity(gpu):
     """FP32 storage and arithmetic against the FP64 oracle: velocity within 1e-5 U0 after
-    200 steps; after the full 2000 steps within 2e-4 U0.  The longer bound follows from
-    the flow's own amplification of rounding: the FP64 run departs from the oracle by
-    ~1.5e3 unit roundoffs after 2000 steps (1.7e-13 U0), which at the FP32 unit roundoff
-    (6e-8) is ~9e-5 U0."""
+    200 steps and after the full 2000 steps.  Unbiased rounding at FP32's unit roundoff
+    stays well inside that bound over the run (independent relative noise of 2^-24 on
+    the stored populations departs by about 2.5e-6 U0), while a coherent bias of that
+    size does not (about 1.2e-4 U0): the CPU pin test_fp32_rounding_model_of_the_
+    imposed_oscillation holds both numbers."""
     from oracle import oracle as orc
     wl = W.imposed_oscillation(storage="fp32")
     _flush("imposed oscillation fp32")
     o = orc.OracleSim(wl["spec"], wl["body"])
     g = gpu.Sim(wl["spec"], wl["body"])
     U0 = wl["U0"]
-    for steps, tol in ((200, 1e-5), (1800, 2e-4)):
+    for steps, tol in ((200, 1e-5), (1800, 1e-5)):
         ro = o.step(steps)
         g.step(steps)
         rg = g.forces()
@@ -582,3 +593,31 @@ def test_bgk_collision_step_by_step_fp64(gpu, bcname, bodykind):
     spec.update(collision="bgk", rates=(1.1, 1.25, 1.8, 1.0 / 0.62))
     body = None if bodykind == "none" else body_of(bodykind, nx, ny, False)
     run_pair(gpu, spec, body, steps=6, seed=4321)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
+@pytest.mark.parametrize("rows,tile", [(1, 256), (4, 512)])
+def test_layouts_are_bitwise_equal(gpu, storage, bcname, rows, tile):
+    """The row-interleaved and the planar population layouts change addresses only:
+    populations and every record field agree bitwise (a free body, a ragged last tile
+    column and tile row)."""
+    nx, ny = 601, 43
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04, storage=storage,
+                   g=(2e-5, -1e-5) if bcname == "periodic" else (0.0, 0.0))
+    spec.update(rows_per_tile=rows, tile_width=tile)
+    b = W.fixed_disc(14.0, 255.6, 19.3)
+    b.update(mode="free", free_mask=7, mass=300.0, inertia=2000.0, k=(0.01, 0.01, 0.0),
+             q0=(255.6, 19.3, 0.0), force_model="vp+mem")
+    f0 = W.random_populations(nx, ny, seed=31, amp=0.05)
+    out = []
+    for layout in ("rows", "planes"):
+        g = gpu.Sim(dict(spec, layout=layout), b)
+        assert g.layout_name() == layout
+        g.set_populations(f0)
+        g.step(12)
+        out.append((g.get_populations(), g.forces()))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for key in ("fvp", "tvp", "pin", "fh", "th", "q", "v", "fmem", "tmem"):
+        assert np.array_equal(out[0][1][key], out[1][1][key]), key
