@@ -73,6 +73,8 @@ def parse():
                     choices=("auto", "given", "largest_first", "interleaved"),
                     help="batch_sweep: tile schedule order (auto: autotune)")
     ap.add_argument("--layout", default="auto", choices=("auto", "rows", "planes"))
+    ap.add_argument("--finalize", default="auto", choices=("auto", "tiles", "kernel"),
+                    help="how the body state is finalized (auto: autotune)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -90,7 +92,7 @@ DEFAULT_STEPS = {"batch_sweep": 4000, "free_viv": 20000, "sedimentation": 10000,
 
 def pinned(args):
     return args.rows != 0 or args.store != "auto" or args.tile_width != 0 or \
-        (args.workload == "batch_sweep" and args.order != "auto")
+        args.finalize != "auto" or (args.workload == "batch_sweep" and args.order != "auto")
 
 
 def cpu_info():
@@ -252,10 +254,23 @@ def split_warmup(warmup, graph_steps):
     return warmup - post, post
 
 
+def copy_calibration():
+    """One device copy of 256 MiB: the scale for the HBM byte counters."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run_batch(args):
     import torch
     from paper_1905_05110_amd import workloads as W
     from paper_1905_05110_amd import vplbm
+
+    if args.copy_calibration:
+        copy_calibration()
 
     steps = args.steps or DEFAULT_STEPS["batch_sweep"]
     sweep = W.batch_sweep(storage=args.storage)
@@ -266,6 +281,7 @@ def run_batch(args):
         batch = vplbm.Batch(members, storage=args.storage, rows=args.rows, store=args.store,
                             history_cap=4096, stream=stream.cuda_stream,
                             tile_width=args.tile_width, layout=args.layout,
+                            finalize=args.finalize,
                             order="largest_first" if args.order == "auto" else args.order)
         w_pre, w_post = split_warmup(args.warmup, args.graph_steps)
         print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
@@ -276,7 +292,7 @@ def run_batch(args):
         tuned = None
         if not args.no_autotune and not pinned(args):
             print("autotune", file=sys.stderr, flush=True)
-            tuned = batch.autotune(trial_steps=20)
+            tuned = batch.autotune(trial_steps=64)
         b_rows, b_nt, b_tile = batch.sims[0].launch_config()
         order = batch.order_name()
         if args.graph_steps:
@@ -288,11 +304,12 @@ def run_batch(args):
         region_ms, wall = timed(stream, batch.step, steps)
         batch.sync()
         layout = batch.sims[0].layout_name()
+        nfin = sum(m.finalize_by_kernel() for m in batch.sims)
         batch.close()
     avg_kernel_s = region_ms * 1e-3 / steps  # one launch per step
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
-    key = "batch_sweep_64 %s %s %d %d %d %s" % (args.storage, layout, b_rows, int(bool(b_nt)),
-                                               b_tile, order)
+    key = "batch_sweep_64 %s %s %d %d %d %s %d" % (args.storage, layout, b_rows, int(bool(b_nt)),
+                                                  b_tile, order, int(nfin > 0))
     out = {
         "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step, batched runs)",
         "value": round(nodes * steps / (region_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
@@ -302,7 +319,9 @@ def run_batch(args):
         "config": {"workload": "batch_sweep_64", "runs": len(members), "nodes": nodes,
                    "storage": args.storage, "layout": layout, "graph_steps": args.graph_steps,
                    "rows_per_tile": b_rows, "nontemporal_stores": bool(b_nt),
-                   "tile_width": b_tile, "order": order, "autotuned": tuned is not None},
+                   "tile_width": b_tile, "order": order,
+                   "finalize_by_kernel": nfin, "launches_per_step": 1 + int(nfin > 0),
+                   "autotuned": tuned is not None},
         "roofline": roofline(args, bytes_per_launch, avg_kernel_s,
                              "k_step<%s> (batched)" % args.storage, key),
         "wall_s": round(wall, 3),
@@ -332,14 +351,10 @@ def run_single(args):
     wl = {"free_viv": W.free_viv, "sedimentation": W.sedimentation,
           "roofline": W.roofline_grid}[args.workload](storage=args.storage)
     spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store,
-                tile_width=args.tile_width, layout=args.layout)
+                tile_width=args.tile_width, layout=args.layout, finalize=args.finalize)
     nodes = spec["nx"] * spec["ny"]
     if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         sim = vplbm.Sim(spec, wl["body"], torch_memory=True, history_cap=1 << 16)
@@ -361,10 +376,12 @@ def run_single(args):
         region_ms, wall = timed(stream, sim.step, steps)
         sim.sync()
         layout = sim.layout_name()
+        fin = sim.finalize_by_kernel()
     avg_kernel_s = region_ms * 1e-3 / steps  # one step-kernel launch per step
     bytes_per_launch = BYTES_PER_NODE[args.storage] * nodes
     name, body = SINGLE[args.workload]
-    key = "%s %s %s %d %d %d -" % (name, args.storage, layout, rows, int(bool(nt)), tile)
+    key = "%s %s %s %d %d %d - %d" % (name, args.storage, layout, rows, int(bool(nt)), tile,
+                                      int(fin))
     out = {
         "metric": "MLUPS (D2Q9 MRT + volume penalization, full FSI step)",
         "value": round(nodes * steps / (region_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
@@ -374,6 +391,7 @@ def run_single(args):
         "config": {"workload": name, "nx": spec["nx"], "ny": spec["ny"], "storage": args.storage,
                    "layout": layout, "body": body, "graph_steps": args.graph_steps,
                    "rows_per_tile": rows, "nontemporal_stores": bool(nt), "tile_width": tile,
+                   "finalize_by_kernel": fin, "launches_per_step": 1 + int(fin),
                    "autotuned": tuned is not None},
         "roofline": roofline(args, bytes_per_launch, avg_kernel_s, "k_step<%s>" % args.storage,
                              key),
@@ -437,9 +455,9 @@ def run_adjoint(args):
     fwd, bwd = statistics.median(tf), statistics.median(tb)
     adj_us, step_us = adj.time_kernels(reps=400)
     esize = {"fp32": 4, "fp64": 8}[args.storage]
-    # adjoint step per node: 9 state reads (re-pull), 9 adjoint reads, 9 adjoint writes,
-    # dJ/dchi read and write
-    adj_bytes = nodes * 29 * esize
+    # adjoint step per node: 9 state reads (re-pull), 9 adjoint reads, 9 adjoint writes in
+    # the storage precision, and the FP64 dJ/dchi accumulator read and written
+    adj_bytes = nodes * (27 * esize + 16)
     achieved = adj_bytes / (adj_us * 1e-6) / 1e9
     out = {
         "metric": "adjoint/forward time ratio (gradient of time-averaged drag)",

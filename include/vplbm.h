@@ -87,6 +87,16 @@ enum { LBM_STORE_AUTO = 0, LBM_STORE_PLAIN = 1, LBM_STORE_NONTEMPORAL = 2 };
  * results are bitwise the same in either. */
 enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_ROWS = 1, LBM_LAYOUT_PLANES = 2 };
 
+/* Where the body state of a step is made final.  The tiles that meet the body write
+ * partial FP64 force sums; the next step needs their total (and the rigid-body update it
+ * drives) before it can place the body.
+ *   TILES   every tile of the next step that meets the body adds all the slots itself
+ *           (no extra launch; for a body over P tiles, P^2 slot reads per step);
+ *   KERNEL  a one-workgroup launch after each step adds them once and writes the state;
+ *   AUTO    KERNEL when the body's tiles number more than 512, else TILES.
+ * Both add the slots in the same fixed order: results are bitwise the same. */
+enum { LBM_FINALIZE_AUTO = 0, LBM_FINALIZE_TILES = 1, LBM_FINALIZE_KERNEL = 2 };
+
 /* Collision operator.  MRT relaxes the moments of Eq. (9) at the rates of lbm_rates
  * (Eqs. (8), (16)); BGK (Sec. 2.2, Eqs. (11)-(12) with Guo's source) relaxes every
  * population at 1/tau = s_nu, which is MRT with all rates equal to s_nu: with it,
@@ -154,6 +164,7 @@ typedef struct {
                               a launch choice: results of different settings agree to
                               rounding (the FP64 force sums follow the tile order). */
     int layout;            /* LBM_LAYOUT_AUTO (default), _ROWS or _PLANES */
+    int finalize;          /* LBM_FINALIZE_AUTO (default), _TILES or _KERNEL */
 } lbm_opts;
 
 typedef struct {
@@ -257,15 +268,17 @@ int64_t lbm_step_index(const lbm_sim* sim);
 int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms);
 
 /* Chooses the launch configuration of the step kernel (rows per tile 1/2/4, plain or
- * nontemporal stores, 256 or 512 columns per tile) by timing trial_steps steps of each
- * candidate on a scratch
- * simulation of the same grid, storage and body, started from a copy of sim's current
- * populations and outflow memory (call it once the flow has developed: the uniform
- * start state is exactly zero in offsets and moves faster than a developed flow), and
- * applies it to sim (whose state is not touched).  cache_path (may be NULL) names a JSON-lines file: a configuration found
- * there for this device, storage and grid is applied without timing, and a newly
- * timed one is appended.  Outputs (each may be NULL): the chosen rows, nt flag, and
- * the measured time per step in microseconds (-1 when taken from the cache). */
+ * nontemporal stores, 256 or 512 columns per tile and, with a body, how its state is
+ * finalized) by timing each candidate on a scratch simulation of the same grid, storage
+ * and body, started from a copy of sim's current populations and outflow memory (call it
+ * once the flow has developed: the uniform start state is exactly zero in offsets and
+ * moves faster than a developed flow): two replays of a captured graph of trial_steps
+ * steps (rounded down to even, at least 2), the faster counting.  It then applies the
+ * fastest to sim (whose state is not touched).  cache_path (may be NULL) names a
+ * JSON-lines file: a configuration found there for this device, storage and grid is
+ * applied without timing, and a newly timed one is appended.  Outputs (each may be
+ * NULL): the chosen rows, nt flag, and the measured time per step in microseconds (-1
+ * when taken from the cache). */
 int lbm_autotune(lbm_sim* sim, int trial_steps, const char* cache_path, int* rows_out,
                  int* nt_out, double* us_out);
 
@@ -276,6 +289,10 @@ int lbm_launch_config(const lbm_sim* sim, int* rows_out, int* nt_out, int* tile_
 
 /* The population layout in use: LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES (never AUTO). */
 int lbm_layout(const lbm_sim* sim, int* layout_out);
+
+/* 1 if the body state is made final by a separate launch after each step (see
+ * LBM_FINALIZE_*), else 0 (also without a body). */
+int lbm_finalize_by_kernel(const lbm_sim* sim, int* kernel_out);
 
 /* Serialises the full state (populations, outflow memory, body, step index) into a
  * host buffer; with buf NULL only *size_out is set.  lbm_load restores a state saved
@@ -313,6 +330,9 @@ typedef struct {
     int tile_width;     /* 0 (default: 256), 256 or 512 */
     int layout;         /* LBM_LAYOUT_AUTO: each member's own opts->layout; else every
                            member takes this one */
+    int finalize;       /* LBM_FINALIZE_AUTO: each member's own opts->finalize; else every
+                           member takes this one (the members that finalize by kernel share
+                           one launch per step) */
 } lbm_batch_opts;
 
 void lbm_default_batch_opts(lbm_batch_opts* o);
@@ -341,9 +361,11 @@ int lbm_batch_size(const lbm_batch* batch);
  * (the columns per tile stay as they are). */
 int lbm_batch_configure(lbm_batch* batch, int rows, int store_mode, int order);
 
-/* Chooses rows, store mode, columns per tile and order by timing trial_steps steps of
- * each candidate on a scratch copy of the batch, then applies them (members' states are
- * not touched; lbm_launch_config on a member reports the choice).
+/* Chooses rows, store mode, columns per tile, order and (with bodies) how the body
+ * states are finalized by timing each candidate on a scratch copy of the batch started
+ * from the members' current states (as lbm_autotune: the faster of two replays of a
+ * captured graph of trial_steps steps), then applies them (members' states are not
+ * touched; lbm_launch_config and lbm_finalize_by_kernel on a member report the choice).
  * Outputs may be NULL; us_out is the time per batch step in microseconds. */
 int lbm_batch_autotune(lbm_batch* batch, int trial_steps, int* rows_out, int* nt_out,
                        int* order_out, double* us_out);
@@ -387,6 +409,15 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
 
 /* Moves the body (mode FIXED); the next forward run starts again from the initial state. */
 int lbm_adjoint_set_body(lbm_adjoint* adj, const lbm_body* body);
+
+/* Adds a field to the body's indicator in the forward run: chi(i, j) = the disc's chi
+ * + field[j][i] at every step (the additive indicator of a smoothed chi; dJ/dchi of
+ * lbm_adjoint_gradient is the derivative with respect to it).  field is FP64 [ny][nx]
+ * host memory, zero outside the body's box (the nodes within the disc's reach plus one
+ * of its centre, where its own indicator may vary), else LBM_ERR_ARG; NULL removes it.
+ * lbm_adjoint_set_body removes it too (the box moves with the body).  It takes effect
+ * at the next lbm_adjoint_forward. */
+int lbm_adjoint_set_chi_add(lbm_adjoint* adj, const double* field);
 
 /* Initial state of the forward run: post-collision populations [9][ny][nx] and the
  * outflow memory [3][ny] (directions 3, 6, 7), FP64 host arrays; NULL restores the

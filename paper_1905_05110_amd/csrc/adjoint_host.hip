@@ -380,7 +380,7 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     A->out_bytes = 3 * (size_t)ny * A->tsz;
     A->atx = (nx + TILE_X - 1) / TILE_X;
     const size_t pb = s->pop_bytes, ob = A->out_bytes;
-    const size_t plane_b = (size_t)s->desc.fpitch * ny * A->tsz;  // dJ/dchi, [ny][fpitch]
+    const size_t plane_b = (size_t)s->desc.fpitch * ny * sizeof(double);  // dJ/dchi, [ny][fpitch]
     auto alloc = [&](void** p, size_t bytes) {
         hipError_t e = hipMalloc(p, bytes);
         if (e != hipSuccess) A->err = std::string("hipMalloc: ") + hipGetErrorString(e);
@@ -443,7 +443,7 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     ad.ckpt_out = A->ckpt_out;
     ad.abar[0] = A->abar[0];
     ad.abar[1] = A->abar[1];
-    ad.chibar = A->chibar;
+    ad.chibar = static_cast<double*>(A->chibar);
     ad.tile_acc = A->tile_acc;
     ad.ring = A->ring;
     ad.ring_kn = A->ring_kn;
@@ -471,9 +471,51 @@ int lbm_adjoint_destroy(lbm_adjoint* A) {
     return LBM_OK;
 }
 
+// Removes the additive indicator (its window follows the pose it was set for).
+static void drop_chi_add(lbm_sim* s) {
+    if (s->chi_add_d) {
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipFree(s->chi_add_d);
+    }
+    s->chi_add_d = nullptr;
+    s->chi_win[0] = s->chi_win[2] = 0;
+    s->chi_win[1] = s->chi_win[3] = -1;
+}
+
+int lbm_adjoint_set_chi_add(lbm_adjoint* A, const double* field) {
+    if (!A) return LBM_ERR_ARG;
+    lbm_sim* s = A->sim;
+    A->fwd_done = A->bwd_done = false;
+    if (!field) {
+        drop_chi_add(s);
+        return LBM_OK;
+    }
+    // the window: the nodes where the disc's own indicator may change with its pose
+    const int* w = A->ad.nbox;
+    for (int j = 0; j < A->ny; ++j)
+        for (int i = 0; i < A->nx; ++i) {
+            const double v = field[(size_t)j * A->nx + i];
+            if (!std::isfinite(v)) return afail(A, LBM_ERR_ARG, "non-finite additive indicator");
+            const bool inside = i >= w[0] && i <= w[1] && j >= w[2] && j <= w[3];
+            if (!inside && v != 0.0)
+                return afail(A, LBM_ERR_ARG, "additive indicator non-zero outside the body's box");
+        }
+    const int ww = w[1] - w[0] + 1, wh = w[3] - w[2] + 1;
+    if (ww < 1 || wh < 1) return afail(A, LBM_ERR_ARG, "the body has no box on the grid");
+    std::vector<double> win((size_t)ww * wh);
+    for (int j = 0; j < wh; ++j)
+        for (int i = 0; i < ww; ++i) win[(size_t)j * ww + i] = field[(size_t)(w[2] + j) * A->nx + w[0] + i];
+    drop_chi_add(s);
+    AHIP_TRY(A, hipMalloc((void**)&s->chi_add_d, win.size() * sizeof(double)));
+    AHIP_TRY(A, hipMemcpy(s->chi_add_d, win.data(), win.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (int k = 0; k < 4; ++k) s->chi_win[k] = w[k];
+    return LBM_OK;  // the next forward run sets the body with it
+}
+
 int lbm_adjoint_set_body(lbm_adjoint* A, const lbm_body* b) {
     if (!A || !b) return afail(A, LBM_ERR_ARG, "NULL argument");
     if (b->mode != LBM_BODY_FIXED) return afail(A, LBM_ERR_ARG, "the adjoint needs a FIXED body");
+    drop_chi_add(A->sim);
     int rc = lbm_set_body(A->sim, b);
     if (rc) return afail(A, rc, A->sim->err);
     A->body = *b;
@@ -573,7 +615,7 @@ int lbm_adjoint_backward(lbm_adjoint* A) {
     lbm_sim* s = A->sim;
     A->bwd_done = false;
     int rc = zero_words(A, A->abar[(A->steps) & 1], s->pop_bytes);
-    if (!rc) rc = zero_words(A, A->chibar, (size_t)s->desc.fpitch * s->ny * A->tsz);
+    if (!rc) rc = zero_words(A, A->chibar, (size_t)s->desc.fpitch * s->ny * sizeof(double));
     if (!rc) rc = zero_words(A, A->tile_acc, (size_t)A->atx * A->ny * 3 * sizeof(double));
     if (rc) return rc;
     const int last = A->nseg - 1;

@@ -57,7 +57,7 @@ struct AdjDesc {
     const char* ckpt_pop;   // one checkpoint per segment (state at the segment start)
     const char* ckpt_out;
     void* abar[2];          // Pbar of the two parities, 9 planes of ps values
-    void* chibar;           // dJ/dchi accumulated over the steps, [ny][fpitch]
+    double* chibar;         // dJ/dchi accumulated over the steps, FP64 [ny][fpitch]
     double* tile_acc;       // per tile of the adjoint grid: u_s adjoint sums (x, y, angular)
     const RingSlot* ring;   // ring_k readers per (edge node, direction)
     const int* ring_kn;     // per edge node: the slots it visits (its longest list)
@@ -114,7 +114,7 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         }
         // 2. indicator and rigid velocity at this node
         const double rxg = (double)i - a.pose[0], ryg = (double)j - a.pose[1];
-        const double chi = B.active ? disc_chi(B, disc_d2(rxg, ryg)) : 0.0;
+        const double chi = B.active ? disc_chi(B, disc_d2(rxg, ryg)) + chi_add_at(B, i, j) : 0.0;
         const double usx_d = a.pose[3] - a.pose[5] * ryg;
         const double usy_d = a.pose[4] + a.pose[5] * rxg;
         const T usx = (T)usx_d, usy = (T)usy_d;
@@ -123,8 +123,11 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         T w[NQ];
         const unsigned row = (unsigned)d.pitch;
         const unsigned o0 = (unsigned)j * row + (unsigned)i;
-        T* chib = reinterpret_cast<T*>(a.chibar) + ((long long)j * d.fpitch + i);
-        const T chib_old = gld(chib);
+        // dJ/dchi adds one term per step over the N steps: accumulated in FP64 whatever
+        // the storage, so that the sum carries no rounding beyond its terms' (the pose
+        // gradient takes it against d(chi)/dX, where front and back nearly cancel)
+        double* chib = a.chibar + ((long long)j * d.fpitch + i);
+        const double chib_old = gld(chib);
         if (inner) {
 #pragma unroll
             for (int b = 0; b < NQ; ++b)
@@ -161,17 +164,20 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         const T rho = o.rho, ux = o.ux, uy = o.uy, Gx = o.Gx, Gy = o.Gy;
         const T rx = o.dux - (T)(usx_d - d.u0x), ry = o.duy - (T)(usy_d - d.u0y);
         const T lam = (T)chi * c.inv_eta;
-        // 5. reverse of the collision.  mbar* = M^-T w = diag(1/|row|^2) M w
+        // 5. reverse of the collision.  mbar* = M^-T w = diag(1/|row|^2) M w; the rows of
+        // the conserved moments divide as the forward step does (correctly rounded, see
+        // div_small), so that the sweep is the transpose of the step it reverses rather
+        // than one with a constant relative bias repeated over the N steps
         const T s1234 = (w[1] + w[2]) + (w[3] + w[4]);
         const T s5678 = (w[5] + w[6]) + (w[7] + w[8]);
         const T dx5 = (w[5] - w[6]) + (w[8] - w[7]);
         const T dy5 = (w[5] + w[6]) - (w[7] + w[8]);
-        const T ms0 = (w[0] + s1234 + s5678) * T(1.0 / 9.0);
+        const T ms0 = div_small(w[0] + s1234 + s5678, T(9), T(1.0 / 9.0));
         const T ms1 = (T(2) * s5678 - T(4) * w[0] - s1234) * T(1.0 / 36.0);
         const T ms2 = (T(4) * w[0] - T(2) * s1234 + s5678) * T(1.0 / 36.0);
-        const T ms3 = ((w[1] - w[3]) + dx5) * T(1.0 / 6.0);
+        const T ms3 = div_small((w[1] - w[3]) + dx5, T(6), T(1.0 / 6.0));
         const T ms4 = (dx5 - T(2) * (w[1] - w[3])) * T(1.0 / 12.0);
-        const T ms5 = ((w[2] - w[4]) + dy5) * T(1.0 / 6.0);
+        const T ms5 = div_small((w[2] - w[4]) + dy5, T(6), T(1.0 / 6.0));
         const T ms6 = (dy5 - T(2) * (w[2] - w[4])) * T(1.0 / 12.0);
         const T ms7 = ((w[1] + w[3]) - (w[2] + w[4])) * T(0.25);
         const T ms8 = ((w[5] + w[7]) - (w[6] + w[8])) * T(0.25);
@@ -239,8 +245,8 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
         }
 #pragma unroll
         for (int b = 0; b < NQ; ++b) gst(Aout + (long long)b * ps + o0, pb[b]);
-        gst(chib, chib_old + lamb * c.inv_eta);
-        if (chi > 0.0) {  // where chi = 0 the step does not depend on u_s
+        gst(chib, chib_old + (double)(lamb * c.inv_eta));
+        if (chi != 0.0) {  // where chi = 0 the step does not depend on u_s
             usum[0] = (double)usbx;
             usum[1] = (double)usby;
             usum[2] = (double)usby * rxg - (double)usbx * ryg;
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(TILE_X) void k_adj_reduce(const SimDesc* __restrict
     const SimDesc& d = *dp;
     const AdjDesc& a = *ap;
     const BodyDev& B = *d.body;
-    const S* chib = reinterpret_cast<const S*>(a.chibar);
+    const double* chib = a.chibar;
     double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int bw = a.nbox[1] - a.nbox[0] + 1, bh = a.nbox[3] - a.nbox[2] + 1;
     const long long nb = (bw > 0 && bh > 0) ? (long long)bw * bh : 0;
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(TILE_X) void k_adj_reduce(const SimDesc* __restrict
         const int i = a.nbox[0] + (int)(k % bw), j = a.nbox[2] + (int)(k / bw);
         double dX, dY;
         chi_pose_derivative(B, (double)i - a.pose[0], (double)j - a.pose[1], dX, dY);
-        const double cb = (double)chib[(long long)j * d.fpitch + i];
+        const double cb = chib[(long long)j * d.fpitch + i];
         t[0] += cb * dX;
         t[1] += cb * dY;
     }
@@ -355,7 +361,7 @@ __global__ void k_adj_export(const SimDesc* __restrict__ dp, const AdjDesc* __re
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     out[(long long)j * d.nx + i] =
-        (double)reinterpret_cast<const S*>(ap->chibar)[(long long)j * d.fpitch + i];
+        ap->chibar[(long long)j * d.fpitch + i];
 }
 
 // Launch interface, instantiated for S = double and float in adj_<storage>.hip.

@@ -93,6 +93,11 @@ struct BodyDev {
     double mass, inertia;
     double k[3], c[3], q0[3], fext[3];
     double amp, freq, y0, phase;
+    // optional additive indicator (FP64, row-major over the node window cwin = (i0, i1,
+    // j0, j1), which lies inside the body's participating tiles): chi(i, j) becomes the
+    // disc's indicator plus chi_add there; used by the adjoint, whose body is fixed
+    const double* chi_add;
+    int cwin[4];
     // State of step n in st[n & 1].  Step n's kernel derives it from st[(n - 1) & 1] and
     // the partial sums of step n - 1 (every tile that needs it, identically) unless the
     // host or a flush already wrote it ("fresh").
@@ -531,6 +536,8 @@ __device__ __forceinline__ double disc_chi(const Body& B, double d2) {
 struct DiscParams {
     int active, smooth;
     double R, R2, delta;
+    const double* chi_add;
+    int cwin[4];
 };
 __device__ __forceinline__ DiscParams disc_params(const BodyDev* B) {
     DiscParams q;
@@ -539,7 +546,17 @@ __device__ __forceinline__ DiscParams disc_params(const BodyDev* B) {
     q.R = gld(&B->R);
     q.R2 = gld(&B->R2);
     q.delta = gld(&B->delta);
+    q.chi_add = gld(&B->chi_add);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q.cwin[k] = gld(&B->cwin[k]);
     return q;
+}
+
+// The additive indicator at node (i, j): the window's value, 0 outside it or without one.
+template <class Body>
+__device__ __forceinline__ double chi_add_at(const Body& B, int i, int j) {
+    if (!B.chi_add || i < B.cwin[0] || i > B.cwin[1] || j < B.cwin[2] || j > B.cwin[3]) return 0.0;
+    return B.chi_add[(long long)(j - B.cwin[2]) * (B.cwin[1] - B.cwin[0] + 1) + (i - B.cwin[0])];
 }
 
 // Tile range (inclusive) of the tiles that meet the support of the body; all its
@@ -940,14 +957,14 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
                 const double rx = (double)i - pose[0], ry = (double)j - pose[1];
                 const double d2 = disc_d2(rx, ry);
                 if (B.active) {
-                    chi = disc_chi(B, d2);
-                    if (chi > 0.0) {
+                    chi = disc_chi(B, d2) + chi_add_at(B, i, j);
+                    if (chi != 0.0) {
                         const double om = pose[5];
                         dsx = (pose[3] - om * ry) - d.u0x;
                         dsy = (pose[4] + om * rx) - d.u0y;
                     }
                 }
-                if (chi > 0.0) {
+                if (chi != 0.0) {
                     collide<T, true>(c, g, (T)chi, (T)dsx, (T)dsy, out, o);
                     const double dFx = (double)o.dFx, dFy = (double)o.dFy;
                     const double jx = (double)o.jgx + d.u0x, jy = (double)o.jgy + d.u0y;
@@ -1088,7 +1105,7 @@ __device__ __forceinline__ void sum_slots(const double* __restrict__ slots, int 
     __syncthreads();
 }
 
-__device__ __forceinline__ int box_count(const int b[4]) { return (b[1] - b[0] + 1) * (b[3] - b[2] + 1); }
+__host__ __device__ __forceinline__ int box_count(const int b[4]) { return (b[1] - b[0] + 1) * (b[3] - b[2] + 1); }
 
 // The body update at the end of step n - 1 (Sec. 2.3, Eqs. (23)-(24); RK4 of
 // Algorithm 1), as every participating tile of step n and the flush kernel compute it:

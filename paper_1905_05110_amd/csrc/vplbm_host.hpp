@@ -95,6 +95,10 @@ struct lbm_sim {
     hipGraph_t graph = nullptr;
     bool in_batch = false;  // member of an lbm_batch: stepped, configured and freed by it
     int row_shift = 0;      // first tile row dispatched (the body's rows come a little later)
+    int fin_req = LBM_FINALIZE_AUTO;  // requested finalization of the body state
+    bool sep_final = false;           // in effect: a one-workgroup launch after each step
+    double* chi_add_d = nullptr;      // additive indicator over chi_win (set by the adjoint)
+    int chi_win[4] = {0, -1, 0, -1};  // its node window (i0, i1, j0, j1)
 };
 
 #define HIP_TRY(sim, expr)                                                             \

@@ -65,6 +65,9 @@ void k_step(const SimDesc* __restrict__ descs,
 }
 
 __global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p);
+// the same for several simulations: workgroup b finalizes descs[members[b]]
+__global__ __launch_bounds__(TILE_X) void k_finalize_batch(const SimDesc* __restrict__ descs,
+                                                           const int* __restrict__ members, int p);
 
 struct Offsets9 {
     double g[NQ];
@@ -126,8 +129,8 @@ __global__ void k_fields(SimDesc d, double* __restrict__ out, int p) {
     double chi = 0.0, dsx = 0.0, dsy = 0.0;
     if (B.active) {
         const double rx = (double)i - st.q[0], ry = (double)j - st.q[1];
-        chi = disc_chi(B, disc_d2(rx, ry));
-        if (chi > 0.0) {
+        chi = disc_chi(B, disc_d2(rx, ry)) + chi_add_at(B, i, j);
+        if (chi != 0.0) {
             dsx = (st.v[0] - st.v[2] * ry) - d.u0x;
             dsy = (st.v[1] + st.v[2] * rx) - d.u0y;
         }

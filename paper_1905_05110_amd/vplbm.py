@@ -24,11 +24,13 @@ STORE = {"auto": 0, "plain": 1, "nontemporal": 2}
 ORDER = {"given": 0, "largest_first": 1, "interleaved": 2}
 OFFSET_REF = {"auto": 0, "initial": 1, "rest": 2}  # auto: rest for 16-bit storage, else initial
 LAYOUT = {"auto": 0, "rows": 1, "planes": 2}
+FINALIZE = {"auto": 0, "tiles": 1, "kernel": 2}
 
 EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
            "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
            "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
            "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_launch_config", "lbm_layout",
+           "lbm_finalize_by_kernel",
            "lbm_save", "lbm_load",
            "lbm_destroy", "lbm_last_error",
            "lbm_default_batch_opts", "lbm_batch_create", "lbm_batch_step",
@@ -36,7 +38,7 @@ EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "l
            "lbm_batch_configure", "lbm_batch_autotune", "lbm_batch_order", "lbm_batch_destroy",
            "lbm_batch_last_error",
            "lbm_default_adjoint_opts", "lbm_adjoint_create", "lbm_adjoint_set_body",
-           "lbm_adjoint_set_initial", "lbm_adjoint_forward", "lbm_adjoint_forces",
+           "lbm_adjoint_set_initial", "lbm_adjoint_set_chi_add", "lbm_adjoint_forward", "lbm_adjoint_forces",
            "lbm_adjoint_backward", "lbm_adjoint_gradient", "lbm_adjoint_time_kernels",
            "lbm_adjoint_destroy", "lbm_adjoint_last_error"]
 
@@ -59,7 +61,7 @@ class Opts(C.Structure):
                 ("offset_ref", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
                 ("hip_stream", C.c_void_p),
                 ("pop_buffers", C.c_void_p * 2), ("collision", C.c_int), ("tile_width", C.c_int),
-                ("layout", C.c_int)]
+                ("layout", C.c_int), ("finalize", C.c_int)]
 
 
 class Body(C.Structure):
@@ -81,7 +83,7 @@ class BatchDesc(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("storage", C.c_int), ("rows_per_tile", C.c_int), ("store_mode", C.c_int),
                 ("order", C.c_int), ("hip_stream", C.c_void_p), ("tile_width", C.c_int),
-                ("layout", C.c_int)]
+                ("layout", C.c_int), ("finalize", C.c_int)]
 
 
 class AdjointOpts(C.Structure):
@@ -129,6 +131,7 @@ def load_library(path=LIB_PATH):
                                C.POINTER(C.c_double)]
     L.lbm_launch_config.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_layout.argtypes = [P, C.POINTER(C.c_int)]
+    L.lbm_finalize_by_kernel.argtypes = [P, C.POINTER(C.c_int)]
     L.lbm_save.argtypes = [P, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbm_load.argtypes = [P, C.c_void_p, C.c_size_t]
     L.lbm_destroy.argtypes = [P]
@@ -156,6 +159,7 @@ def load_library(path=LIB_PATH):
                                      C.POINTER(Body), C.POINTER(AdjointOpts), C.POINTER(P)]
     L.lbm_adjoint_set_body.argtypes = [P, C.POINTER(Body)]
     L.lbm_adjoint_set_initial.argtypes = [P, _DP, _DP]
+    L.lbm_adjoint_set_chi_add.argtypes = [P, _DP]
     L.lbm_adjoint_forward.argtypes = [P, _DP]
     L.lbm_adjoint_forces.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
     L.lbm_adjoint_backward.argtypes = [P]
@@ -198,6 +202,7 @@ def make_opts(spec, stream=None, buffers=None, history_cap=65536):
     o.collision = {"mrt": 0, "bgk": 1}[spec.get("collision", "mrt")]
     o.tile_width = int(spec.get("tile_width", 0))
     o.layout = LAYOUT[spec.get("layout", "auto")]
+    o.finalize = FINALIZE[spec.get("finalize", "auto")]
     o.hip_stream = stream
     if buffers is not None:
         o.pop_buffers[0], o.pop_buffers[1] = buffers
@@ -356,6 +361,12 @@ class Sim:
         self._check(self.L.lbm_layout(self.h, C.byref(v)))
         return {LAYOUT["rows"]: "rows", LAYOUT["planes"]: "planes"}[v.value]
 
+    def finalize_by_kernel(self):
+        """True if the body state is made final by a launch after each step."""
+        v = C.c_int()
+        self._check(self.L.lbm_finalize_by_kernel(self.h, C.byref(v)))
+        return bool(v.value)
+
     def save(self):
         size = C.c_size_t()
         self._check(self.L.lbm_save(self.h, None, 0, C.byref(size)))
@@ -396,7 +407,8 @@ class Batch:
     """
 
     def __init__(self, members, storage="fp32", order="largest_first", rows=0, store="auto",
-                 history_cap=65536, graph_steps=0, stream=None, tile_width=0, layout="auto"):
+                 history_cap=65536, graph_steps=0, stream=None, tile_width=0, layout="auto",
+                 finalize="auto"):
         L = load_library()
         self.L = L
         self.h = None
@@ -422,6 +434,7 @@ class Batch:
         bo.hip_stream = stream
         bo.tile_width = int(tile_width)
         bo.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)
+        bo.finalize = FINALIZE[finalize] if isinstance(finalize, str) else int(finalize)
         h = C.c_void_p()
         rc = L.lbm_batch_create(n, descs, C.byref(bo), C.byref(h))
         if rc != LBM_OK:
@@ -511,6 +524,8 @@ class Adjoint:
         ao.weight_fx, ao.weight_fy = float(weights[0]), float(weights[1])
         ao.use_graphs = 1 if graphs else 0
         self.steps = int(steps)
+        self.generation = 0  # forward runs so far; the autograd Function checks it
+        self._inputs = None  # (centre, additive indicator) of the last forward run
         h = C.c_void_p()
         rc = L.lbm_adjoint_create(self.nx, self.ny, Rates(*[float(x) for x in spec["rates"]]),
                                   float(spec["eta"]), C.byref(self._opts), C.byref(self._body),
@@ -525,8 +540,18 @@ class Adjoint:
         return rc
 
     def set_body(self, body):
+        """Moves the (fixed) body; removes an additive indicator set before."""
         self._body = make_body(body)
         self._check(self.L.lbm_adjoint_set_body(self.h, C.byref(self._body)))
+
+    def set_chi_add(self, field=None):
+        """Additive indicator [ny, nx] (zero outside the body's box), or None."""
+        if field is None:
+            self._check(self.L.lbm_adjoint_set_chi_add(self.h, None))
+            return
+        field = np.ascontiguousarray(field, dtype=np.float64)
+        assert field.shape == (self.ny, self.nx)
+        self._check(self.L.lbm_adjoint_set_chi_add(self.h, _ptr(field)))
 
     def set_initial(self, f=None, outlet=None):
         fp = op = None
@@ -542,6 +567,7 @@ class Adjoint:
 
     def forward(self):
         J = C.c_double()
+        self.generation += 1
         self._check(self.L.lbm_adjoint_forward(self.h, C.byref(J)))
         return J.value
 
@@ -578,25 +604,63 @@ class Adjoint:
             pass
 
 
-def body_position_objective():
-    """A ``torch.autograd.Function`` mapping the body centre (tensor of 2) to J, whose
-    backward runs the adjoint: ``J = Objective.apply(center, adjoint, body)``."""
+def adjoint_objective():
+    """A ``torch.autograd.Function`` for J of an :class:`Adjoint`:
+    ``J = F.apply(center, chi_add, adjoint, body)`` with ``center`` a tensor of 2 (the
+    disc's X, Y) and ``chi_add`` a tensor [ny, nx] added to the disc's indicator (zero
+    outside the body's box; may be None).  Backward runs the adjoint sweep and returns
+    dJ/d(X, Y) and dJ/dchi.  The Function keeps no state of its own between forward and
+    backward: it saves its inputs, and when the adjoint has run another forward pass
+    since (another apply), backward first runs this one's forward again."""
     import torch
+
+    def run_forward(adj, body, c, chi):
+        adj.set_body(dict(body, x=float(c[0]), y=float(c[1])))
+        if chi is not None:
+            adj.set_chi_add(chi)
+        return adj.forward()
 
     class Objective(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, center, adj, body):
-            c = center.detach().double().cpu().numpy()
-            adj.set_body(dict(body, x=float(c[0]), y=float(c[1])))
-            J = adj.forward()
-            ctx.adj = adj
-            ctx.center_like = center
+        def forward(ctx, center, chi_add, adj, body):
+            c = center.detach().double().cpu().numpy().copy()
+            chi = None if chi_add is None else chi_add.detach().double().cpu().numpy().copy()
+            J = run_forward(adj, body, c, chi)
+            ctx.adj, ctx.body, ctx.c, ctx.chi = adj, dict(body), c, chi
+            ctx.generation = adj.generation
+            ctx.has_chi = chi_add is not None
+            ctx.like = center
+            ctx.chi_like = chi_add
             return center.new_tensor(J)
 
         @staticmethod
         def backward(ctx, grad):
-            ctx.adj.backward()
-            g = ctx.adj.gradient(chi=False)["pos"]
-            return grad * ctx.center_like.new_tensor(g), None, None
+            adj = ctx.adj
+            if adj.generation != ctx.generation:  # another forward ran since: redo this one
+                run_forward(adj, ctx.body, ctx.c, ctx.chi)
+            adj.backward()
+            g = adj.gradient(chi=ctx.has_chi)
+            gc = grad * ctx.like.new_tensor(g["pos"])
+            gchi = grad * ctx.chi_like.new_tensor(g["chi"]) if ctx.has_chi else None
+            return gc, gchi, None, None
+
+    return Objective
+
+
+def body_position_objective():
+    """The centre-only form of :func:`adjoint_objective`:
+    ``J = Objective.apply(center, adjoint, body)``."""
+    import torch
+    F = adjoint_objective()
+
+    class Objective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, center, adj, body):
+            return F.forward(ctx, center, None, adj, body)
+
+        @staticmethod
+        def backward(ctx, grad):
+            gc, _, _, _ = F.backward(ctx, grad)
+            return gc, None, None
 
     return Objective

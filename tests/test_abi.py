@@ -61,12 +61,27 @@ def _create(lib, nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3, **kw):
     (dict(tile_width=384), "tile_width"),
     (dict(tile_width=128), "tile_width"),
     (dict(storage="fp16", fp16_scale_log2=20), "fp16_scale"),
+    # population addresses are 32-bit byte offsets: a 24000^2 FP64 grid has planes of
+    # 4.6 GB, an 8192^2 FP64 grid a 4.8 GB buffer (too large for the ROWS layout)
+    (dict(nx=24000, ny=24000, storage="fp64"), "4 GiB"),
+    (dict(nx=8192, ny=8192, storage="fp64", layout="rows"), "4 GiB"),
+    (dict(nx=32768, ny=32768, storage="fp32"), "4 GiB"),
 ])
 def test_invalid_arguments_are_rejected(lib, kw, frag):
     rc, h, msg = _create(lib, **kw)
     assert rc == vplbm.LBM_ERR_ARG
     assert frag in msg
     assert not h.value
+
+
+def test_invalid_layout_and_offset_reference_are_rejected(lib):
+    spec = dict(nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3)
+    for field, value, frag in (("layout", 3, "layout"), ("offset_ref", 3, "offset reference")):
+        o = vplbm.make_opts(spec)
+        setattr(o, field, value)
+        h = C.c_void_p()
+        rc = lib.lbm_create(10, 8, vplbm.Rates(1.6, 1.5, 1.9, 1.2), 1e-3, C.byref(o), C.byref(h))
+        assert rc == vplbm.LBM_ERR_ARG and frag in lib.lbm_last_error(None).decode()
 
 
 def test_null_handles_are_rejected(lib):
@@ -125,9 +140,30 @@ def test_batch_null_arguments_are_rejected(lib):
     assert lib.lbm_batch_sim(None, 0, C.byref(h)) == vplbm.LBM_ERR_ARG
 
 
-def test_batch_struct_layout(lib):
-    assert C.sizeof(vplbm.BatchOpts) == 4 * 4 + 8 + 4 + 4  # tile_width, then padding
-    assert C.sizeof(vplbm.BatchDesc) == 4 * 2 + 8 * 4 + 8 + 8 + 8
+def test_structs_match_the_header(tmp_path):
+    """Sizes and field offsets of the binding's ctypes structures against the C compiler's
+    reading of include/vplbm.h."""
+    import subprocess
+    structs = {"lbm_opts": vplbm.Opts, "lbm_batch_opts": vplbm.BatchOpts,
+               "lbm_batch_desc": vplbm.BatchDesc, "lbm_body": vplbm.Body,
+               "lbm_rates": vplbm.Rates, "lbm_adjoint_opts": vplbm.AdjointOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vplbm.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", inc, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_batch_create_without_device_reports_hip_error(lib):

@@ -169,3 +169,41 @@ def test_batch_autotune_and_sweep(gpu):
     q, v = batch.sims[17].body_state()
     assert np.isfinite(q).all() and np.isfinite(v).all()
     batch.close()
+
+
+@pytest.mark.parametrize("fin", ["tiles", "kernel"])
+def test_finalize_modes_in_a_batch(gpu, fin):
+    """Members whose body state is finalized by the shared launch after each step, or by
+    their own tiles, are bitwise equal to standalone runs finalized either way (graph
+    replay); a body set later on the body-less member joins the shared launch."""
+    members = mixed_members("fp32")
+    batch = gpu.Batch(members, storage="fp32", rows=1, store="plain", graph_steps=8,
+                      finalize=fin)
+    assert all(m.finalize_by_kernel() == (fin == "kernel" and b is not None)
+               for m, (_, b) in zip(batch.sims, members))
+    batch.step(21)
+    batch.sync()
+    other = "tiles" if fin == "kernel" else "kernel"
+    for i, (spec, body) in enumerate(members):
+        s = gpu.Sim(dict(spec, rows_per_tile=1, store_mode="plain", finalize=other), body)
+        s.step(21)
+        m = batch.sims[i]
+        assert np.array_equal(m.get_populations(), s.get_populations()), i
+        if body is not None:
+            rm, rs = m.forces(), s.forces()
+            for key in ("fvp", "tvp", "pin", "fh", "th", "q", "v"):
+                assert np.array_equal(rm[key], rs[key]), (i, key)
+        s.close()
+    if fin == "tiles":
+        batch.close()
+        return
+    spec, _ = members[2]
+    big = W.fixed_disc(40.0, 48.3, 22.1)
+    big.update(mode="free", free_mask=7, mass=3000.0, inertia=9e5)
+    batch.sims[2].set_body(big)
+    batch.step(12)
+    batch.sync()
+    assert batch.sims[2].finalize_by_kernel()
+    r = batch.sims[2].forces()
+    assert len(r) == 12 and np.isfinite(r["fvp"]).all()
+    batch.close()

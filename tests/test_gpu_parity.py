@@ -246,15 +246,18 @@ def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb, rows):
 
 
 @pytest.mark.parametrize("tile", [256, 512])
-def test_body_over_more_tiles_than_a_workgroup_has_threads_fp64(gpu, tile):
+@pytest.mark.parametrize("fin", ["tiles", "kernel"])
+def test_body_over_more_tiles_than_a_workgroup_has_threads_fp64(gpu, tile, fin):
     """A disc of diameter 260 on a 300x300 grid: with one row per tile its participation
     box holds about 540 (256-column tiles) or 270 (512-column) tiles, more than the 256
     threads that add the slots, so each of them adds several.  Three steps between
-    synchronising calls: the derivation inside the step and the flush both run."""
+    synchronising calls: the derivation inside the step (or in the launch after it) and
+    the flush both run."""
     nx, ny = 300, 300
-    _flush("large body tile %d" % tile)
+    _flush("large body tile %d finalize %s" % (tile, fin))
     spec = spec_of(nx, ny, BCS["channel"], u_wall=UWALL, u_conv=0.04)
     spec["tile_width"] = tile
+    spec["finalize"] = fin
     b = W.fixed_disc(260.0, 150.3, 149.6)
     b.update(mode="free", free_mask=7, mass=5e6, inertia=5e9, k=(0.01, 0.01, 0.0),
              q0=(150.3, 149.6, 0.0))
@@ -621,3 +624,27 @@ def test_layouts_are_bitwise_equal(gpu, storage, bcname, rows, tile):
     assert np.array_equal(out[0][0], out[1][0])
     for key in ("fvp", "tvp", "pin", "fh", "th", "q", "v", "fmem", "tmem"):
         assert np.array_equal(out[0][1][key], out[1][1][key]), key
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile", [256, 512])
+def test_finalize_modes_are_bitwise_equal(gpu, storage, tile):
+    """The body state made final by the next step's tiles or by a one-workgroup launch
+    after each step (eager and replayed from graphs): the same fixed-order sums, so
+    populations and every record field agree bitwise."""
+    wl = W.imposed_oscillation(storage=storage, nx=600, ny=90, D=24.0)
+    wl["body"].update(mode="free", free_mask=7, mass=400.0, inertia=4000.0, k=(0.01, 0.01, 0.0),
+                      force_model="vp+mem")
+    res = []
+    for fin, graphs in (("tiles", 0), ("kernel", 0), ("kernel", 8), ("auto", 8)):
+        g = gpu.Sim(dict(wl["spec"], tile_width=tile, finalize=fin), wl["body"],
+                    graph_steps=graphs)
+        assert g.finalize_by_kernel() == (fin == "kernel")  # auto: a small box, in the tiles
+        g.step(3)
+        g.step(37)
+        res.append((g.get_populations(), g.forces()))
+        g.close()
+    for f, r in res[1:]:
+        assert np.array_equal(f, res[0][0])
+        for key in ("fvp", "tvp", "pin", "fh", "th", "q", "v", "fmem", "tmem", "step"):
+            assert np.array_equal(r[key], res[0][1][key]), key
