@@ -232,6 +232,18 @@ int lbm_clear_body(lbm_sim* sim);
 /* Enqueues n >= 0 time steps (Algorithm 1) on the simulation's stream. */
 int lbm_step(lbm_sim* sim, int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): enqueues n >= 0 steps exactly as
+ * lbm_step does with graphs off (eager launches on the simulation's stream; bitwise the
+ * same results and records), allocating nothing.  The step kernels' only scratch memory,
+ * the body's partial force sums (12 FP64 per tile that meets the body), then lives in a
+ * static array of the library (2 MiB per device, held until the process ends) instead
+ * of the simulation's own.  LBM_ERR_ARG if the body spans more tiles than that holds
+ * (10 922, counting one tile of slack each way).  The array is shared by every call on
+ * a device: calls that overlap on one device (other host threads, other streams) race
+ * and must not be made. */
+int lbm_step_static(lbm_sim* sim, int64_t n);
+
 /* Replays captured HIP graphs of k steps (k even, >= 2) inside lbm_step; k = 0 turns
  * graphs off.  Results are identical with and without graphs. */
 int lbm_set_graph_steps(lbm_sim* sim, int k);

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,12 +22,13 @@
 using namespace vplbm;
 
 namespace vplbm {
-__global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p) {
-    finalize_step(*dp, p);
+__global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p,
+                                                     SlotArray sa) {
+    finalize_step(*dp, p, sa);
 }
 __global__ __launch_bounds__(TILE_X) void k_finalize_batch(const SimDesc* __restrict__ descs,
                                                            const int* __restrict__ members, int p) {
-    finalize_step(descs[members[blockIdx.x]], p);
+    finalize_step(descs[members[blockIdx.x]], p, SlotArray{nullptr, 0});
 }
 }  // namespace vplbm
 
@@ -107,20 +109,24 @@ static void update_finalize(lbm_sim* s) {
     }
 }
 
-// One fluid-structure step: one kernel launch (ev0/ev1, optional, bracket it).
-static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+// One fluid-structure step: one kernel launch (ev0/ev1, optional, bracket it); the
+// partial force slots in sa.slots when that is set (lbm_step_static), else the
+// simulation's own.
+static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                       SlotArray sa = SlotArray{nullptr, 0}) {
     const int p = (int)(s->host_step & 1);
     const dim3 grid(s->desc.tiles_x, s->desc.tiles_y);
     if (ev0) HIP_TRY(s, hipEventRecord(ev0, s->stream));
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, s->desc.tile_w, p, s->stream, s->row_shift);
+        Launch<S>::step(s->desc_d, grid, s->rows, s->nt, s->desc.tile_w, p, s->stream, s->row_shift,
+                        sa);
         return LBM_OK;
     });
     if (ev1) HIP_TRY(s, hipEventRecord(ev1, s->stream));
     if (s->sep_final)  // the state of the next step, made final once for every tile
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TILE_X), 0, s->stream, s->desc_d,
-                           (int)((s->host_step + 1) & 1));
+                           (int)((s->host_step + 1) & 1), sa);
     HIP_TRY(s, hipGetLastError());
     s->host_step += 1;
     return LBM_OK;
@@ -128,13 +134,44 @@ static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nu
 
 // Makes the body state of the next step final and writes the last step's record
 // (the step kernels defer that work to their successor).  Enqueued on the stream.
-static int flush_state(lbm_sim* s) {
+static int flush_state(lbm_sim* s, SlotArray sa = SlotArray{nullptr, 0}) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TILE_X), 0, s->stream, s->desc_d,
-                       (int)(s->host_step & 1));
+                       (int)(s->host_step & 1), sa);
     HIP_TRY(s, hipGetLastError());
     return LBM_OK;
 }
 
+// ---- partial force slots in a static device array, for lbm_step_static ------------------
+// Callers that cannot allocate device memory (graph capture, serving loops) step with
+// the partial slots here instead of the simulation's own array; each device holds its own
+// copy for the life of the process.  STATIC_SLOT_DOUBLES / 2 per parity: 10 922 tiles of
+// 12 sums.
+constexpr long long STATIC_SLOT_DOUBLES = 1LL << 18;  // 2 MiB
+static __device__ __align__(256) double scratch[STATIC_SLOT_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// The device address of this device's `scratch` (the array's name in host code stands
+// for it but is not a device address), looked up once per device with it current.
+static int static_slots(lbm_sim* s, SlotArray& sa) {
+    int dev = -1;
+    HIP_TRY(s, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(s, LBM_ERR_STATE, "device index beyond the static slot table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(s, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(s, LBM_ERR_HIP, "hipGetSymbolAddress returned no address");
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    sa.slots = g_scratch_ptr[dev];
+    sa.stride = STATIC_SLOT_DOUBLES / 2;
+    return LBM_OK;
+}
 
 extern "C" {
 
@@ -613,6 +650,33 @@ int lbm_step(lbm_sim* s, int64_t n) {
         if (rc) return rc;
     }
     return LBM_OK;
+}
+
+int lbm_step_static(lbm_sim* s, int64_t n) {
+    if (!s) return LBM_ERR_ARG;
+    if (s->in_batch) return reject_member(s);
+    if (n < 0) return fail(s, LBM_ERR_ARG, "n must be >= 0");
+    if (s->has_body) {
+        // a step's slots: one per tile of its participation box; the box of a moving body
+        // spans at most one more tile each way than that of the pose set last
+        const BodyState& st = s->body_h.st[s->host_step & 1];
+        int box[4];
+        body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, s->body_h, st.q[0], st.q[1], box);
+        const long long need = (long long)(box[1] - box[0] + 3) * (box[3] - box[2] + 3) * NRED;
+        if (need > STATIC_SLOT_DOUBLES / 2)
+            return fail(s, LBM_ERR_ARG, "the body's tiles need more partial slots than the static array holds (" +
+                                            std::to_string(STATIC_SLOT_DOUBLES / 2 / NRED) + " tiles)");
+    }
+    SlotArray sa;
+    int rc = static_slots(s, sa);
+    if (rc) return rc;
+    // the pending state is made final from the simulation's own slots; the steps then
+    // write and read the static ones, and the last is made final from them, so that later
+    // steps of either kind find a final state and never read the other kind's slots
+    rc = flush_state(s);
+    for (int64_t k = 0; k < n && rc == LBM_OK; ++k) rc = launch_step(s, nullptr, nullptr, sa);
+    if (rc == LBM_OK && n > 0) rc = flush_state(s, sa);
+    return rc;
 }
 
 int lbm_step_timed(lbm_sim* s, int64_t n, double* kernel_ms, double* region_ms) {

@@ -1217,8 +1217,19 @@ __device__ __forceinline__ void store_state(BodyState& cur, const BodyState& pre
 // The caller maps workgroups to tiles (the host rotates the rows so that those of the
 // body are dispatched early, a little into the grid: their longer work then overlaps
 // the rest of the grid instead of extending the end of the kernel).
+// Where a step's partial force slots live: the simulation's own array, or (slots != null)
+// an array the caller names, whose two parities lie `stride` doubles apart.
+struct SlotArray {
+    double* slots;
+    long long stride;
+};
+__device__ __forceinline__ double* slot_base(const SimDesc& d, SlotArray sa, int parity) {
+    return sa.slots ? sa.slots + (long long)parity * sa.stride
+                    : d.partials + (long long)parity * d.part_stride;
+}
+
 template <class S, int ROWS, bool NT, int TW>
-__device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p) {
+__device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p, SlotArray sa) {
     using T = typename Codec<S>::T;
     __shared__ double red[TW / 64][NRED];
     __shared__ double pose_set[6];
@@ -1227,7 +1238,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     // The step's scalars, then the participation box and whether this step's state is
     // final already, then the first row's populations.
     const TileScalars<T> ts = tile_scalars<S>(d, p);
-    const double* prev_slots = d.partials + (long long)(p ^ 1) * d.part_stride;
+    const double* prev_slots = slot_base(d, sa, p ^ 1);
     // The box is read with vector-memory (buffer) loads whose values stay in vector
     // registers until the pull has been issued: a uniform load result is otherwise
     // moved to scalar registers, with a wait for it, where it is loaded, and a scalar
@@ -1307,7 +1318,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
         double s = red[0][k];
         for (int w = 1; w < TW / 64; ++w) s += red[w][k];
         const int slot = (ty - by0) * (bx1 - bx0 + 1) + (tx - bx0);
-        d.partials[(long long)p * d.part_stride + (long long)slot * NRED + k] = s;
+        slot_base(d, sa, p)[(long long)slot * NRED + k] = s;
     }
     // the writer's global stores come last: no barrier waits for them
     if (writer && threadIdx.x == 0) {
@@ -1327,12 +1338,12 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
 // Flush (one workgroup): make the state of step n (parity p) final on the host's
 // request, writing the record of step n - 1.  Does nothing when the state is fresh
 // already, so it may be launched any number of times.
-__device__ __forceinline__ void finalize_step(const SimDesc& d, int p) {
+__device__ __forceinline__ void finalize_step(const SimDesc& d, int p, SlotArray sa) {
     __shared__ double red[NWAVE][NRED];
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
     if (B.st[p].fresh) return;  // uniform
-    derive_body(d, p, red, bs, d.partials + (long long)(p ^ 1) * d.part_stride,
+    derive_body(d, p, red, bs, slot_base(d, sa, p ^ 1),
                 B.st[p ^ 1].part_box);
     if (threadIdx.x == 0) {
         const BodyState& prev = B.st[p ^ 1];

@@ -15,9 +15,10 @@ template <class S>
 struct Launch {
     // the kernel of one time step (parity p; rows per tile 1, 2 or 4; nt selects
     // nontemporal stores; tile_w columns per tile, TILE_X or TILE_WIDE; tile rows
-    // dispatched from row_shift on, 0 <= row_shift < grid.y)
+    // dispatched from row_shift on, 0 <= row_shift < grid.y; the partial force slots in
+    // sa.slots when that is set, else in the simulation's own array)
     static void step(const SimDesc* dd, dim3 grid, int rows, bool nt, int tile_w, int p,
-                     hipStream_t st, int row_shift = 0);
+                     hipStream_t st, int row_shift = 0, SlotArray sa = SlotArray{nullptr, 0});
     // one time step of several simulations in one launch: workgroup b handles the tile
     // sched[b] = (simulation, by << 16 | bx) of descs[simulation]
     static void step_batch(const SimDesc* descs, const int2* sched, int nsched, int rows, bool nt,
@@ -42,7 +43,7 @@ template <class S, int ROWS, bool NT, int TW>
 __global__ __launch_bounds__(TW) __attribute__((amdgpu_waves_per_eu(step_waves<S, ROWS>())))
 void k_step(const SimDesc* __restrict__ descs,
                                                  const int2* __restrict__ sched, int p,
-                                                 int row_shift) {
+                                                 int row_shift, SlotArray sa) {
     const SimDesc* d;
     int tx, ty;
     if (sched) {  // entry: (simulation, ty << 16 | tx)
@@ -61,10 +62,11 @@ void k_step(const SimDesc* __restrict__ descs,
         ty = (int)blockIdx.y + row_shift;
         if (ty >= (int)gridDim.y) ty -= (int)gridDim.y;
     }
-    step_tile<S, ROWS, NT, TW>(*d, tx, ty, p);
+    step_tile<S, ROWS, NT, TW>(*d, tx, ty, p, sa);
 }
 
-__global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p);
+__global__ __launch_bounds__(TILE_X) void k_finalize(const SimDesc* __restrict__ dp, int p,
+                                                     SlotArray sa);
 // the same for several simulations: workgroup b finalizes descs[members[b]]
 __global__ __launch_bounds__(TILE_X) void k_finalize_batch(const SimDesc* __restrict__ descs,
                                                            const int* __restrict__ members, int p);
@@ -148,40 +150,42 @@ inline dim3 grid_rows(const SimDesc& d) { return dim3((d.nx + 255) / 256, d.ny);
 
 template <class S, bool NT, int TW>
 static void launch_step_tw(const SimDesc* dd, const int2* sched, dim3 grid, int rows, int p,
-                           hipStream_t st, int row_shift) {
+                           hipStream_t st, int row_shift, SlotArray sa) {
     switch (rows) {
-        case 1: hipLaunchKernelGGL((k_step<S, 1, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift); break;
-        case 2: hipLaunchKernelGGL((k_step<S, 2, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift); break;
-        default: hipLaunchKernelGGL((k_step<S, 4, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift); break;
+        case 1: hipLaunchKernelGGL((k_step<S, 1, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift, sa); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift, sa); break;
+        default: hipLaunchKernelGGL((k_step<S, 4, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift, sa); break;
     }
 }
 
 template <class S, bool NT>
 static void launch_step_rows(const SimDesc* dd, const int2* sched, dim3 grid, int rows, int tile_w,
-                             int p, hipStream_t st, int row_shift) {
+                             int p, hipStream_t st, int row_shift, SlotArray sa) {
     if (tile_w == TILE_WIDE)
-        launch_step_tw<S, NT, TILE_WIDE>(dd, sched, grid, rows, p, st, row_shift);
+        launch_step_tw<S, NT, TILE_WIDE>(dd, sched, grid, rows, p, st, row_shift, sa);
     else
-        launch_step_tw<S, NT, TILE_X>(dd, sched, grid, rows, p, st, row_shift);
+        launch_step_tw<S, NT, TILE_X>(dd, sched, grid, rows, p, st, row_shift, sa);
 }
 
 // Body of one translation unit: defines Launch<S>.
 #define VPLBM_DEFINE_LAUNCH(S)                                                                \
     template <>                                                                             \
     void Launch<S>::step(const SimDesc* dd, dim3 grid, int rows, bool nt, int tile_w, int p, \
-                         hipStream_t st, int row_shift) {                                   \
+                         hipStream_t st, int row_shift, SlotArray sa) {                     \
         if (nt)                                                                             \
-            launch_step_rows<S, true>(dd, nullptr, grid, rows, tile_w, p, st, row_shift);   \
+            launch_step_rows<S, true>(dd, nullptr, grid, rows, tile_w, p, st, row_shift, sa); \
         else                                                                                \
-            launch_step_rows<S, false>(dd, nullptr, grid, rows, tile_w, p, st, row_shift);  \
+            launch_step_rows<S, false>(dd, nullptr, grid, rows, tile_w, p, st, row_shift, sa); \
     }                                                                                       \
     template <>                                                                             \
     void Launch<S>::step_batch(const SimDesc* descs, const int2* sched, int nsched, int rows, \
                                bool nt, int tile_w, int p, hipStream_t st) {                \
         if (nt)                                                                             \
-            launch_step_rows<S, true>(descs, sched, dim3(nsched), rows, tile_w, p, st, 0);  \
+            launch_step_rows<S, true>(descs, sched, dim3(nsched), rows, tile_w, p, st, 0,   \
+                                      SlotArray{nullptr, 0});                               \
         else                                                                                \
-            launch_step_rows<S, false>(descs, sched, dim3(nsched), rows, tile_w, p, st, 0); \
+            launch_step_rows<S, false>(descs, sched, dim3(nsched), rows, tile_w, p, st, 0,  \
+                                       SlotArray{nullptr, 0});                              \
     }                                                                                       \
     template <>                                                                             \
     void Launch<S>::fill(const SimDesc& d, const double g[NQ], int buf, hipStream_t st) {   \

@@ -27,7 +27,8 @@ LAYOUT = {"auto": 0, "rows": 1, "planes": 2}
 FINALIZE = {"auto": 0, "tiles": 1, "kernel": 2}
 
 EXPORTS = ["lbm_default_opts", "lbm_pop_bytes", "lbm_create", "lbm_set_body", "lbm_clear_body",
-           "lbm_step", "lbm_set_graph_steps", "lbm_sync", "lbm_forces", "lbm_fields",
+           "lbm_step", "lbm_step_static", "lbm_set_graph_steps", "lbm_sync", "lbm_forces",
+           "lbm_fields",
            "lbm_set_populations", "lbm_get_populations", "lbm_get_body_state",
            "lbm_step_index", "lbm_step_timed", "lbm_autotune", "lbm_launch_config", "lbm_layout",
            "lbm_finalize_by_kernel",
@@ -117,6 +118,7 @@ def load_library(path=LIB_PATH):
     L.lbm_set_body.argtypes = [P, C.POINTER(Body)]
     L.lbm_clear_body.argtypes = [P]
     L.lbm_step.argtypes = [P, C.c_int64]
+    L.lbm_step_static.argtypes = [P, C.c_int64]
     L.lbm_set_graph_steps.argtypes = [P, C.c_int]
     L.lbm_sync.argtypes = [P]
     L.lbm_forces.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
@@ -295,6 +297,11 @@ class Sim:
 
     def step(self, n=1):
         self._check(self.L.lbm_step(self.h, int(n)))
+
+    def step_static(self, n=1):
+        """n steps that allocate nothing (eager launches, the partial force sums in the
+        library's static array); see lbm_step_static."""
+        self._check(self.L.lbm_step_static(self.h, int(n)))
 
     def sync(self):
         self._check(self.L.lbm_sync(self.h))
