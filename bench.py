@@ -73,6 +73,8 @@ def parse():
                     choices=("auto", "given", "largest_first", "interleaved"),
                     help="batch_sweep: tile schedule order (auto: autotune)")
     ap.add_argument("--layout", default="auto", choices=("auto", "rows", "planes"))
+    ap.add_argument("--offset-ref", default="auto", choices=("auto", "initial", "rest"),
+                    help="reference of the stored offsets (auto: rest for 16-bit storage)")
     ap.add_argument("--finalize", default="auto", choices=("auto", "tiles", "kernel"),
                     help="how the body state is finalized (auto: autotune)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -223,7 +225,7 @@ def batch_accuracy(args, vplbm, W):
     res = {}
     for storage in ("fp64", "fp32", "fp16", "bf16"):
         sweep = W.batch_sweep(storage=storage)
-        members = [(w["spec"], w["body"]) for w in sweep]
+        members = [(dict(w["spec"], offset_ref=args.offset_ref), w["body"]) for w in sweep]
         print("accuracy run %s, %d steps" % (storage, args.accuracy_steps), file=sys.stderr,
               flush=True)
         batch = vplbm.Batch(members, storage=storage, graph_steps=64,
@@ -233,7 +235,8 @@ def batch_accuracy(args, vplbm, W):
         res[storage] = sweep_statistics(batch, sweep, args.accuracy_steps)
         batch.close()
     ref = np.array(res["fp64"])
-    out = {"steps": args.accuracy_steps, "fp64_mean_cd_range": [round(ref[:, 0].min(), 4),
+    out = {"steps": args.accuracy_steps, "offset_ref": args.offset_ref,
+           "fp64_mean_cd_range": [round(ref[:, 0].min(), 4),
                                                                   round(ref[:, 0].max(), 4)],
            "fp64_rms_cl_range": [round(ref[:, 1].min(), 4), round(ref[:, 1].max(), 4)]}
     for storage in ("fp32", "fp16", "bf16"):
@@ -274,7 +277,7 @@ def run_batch(args):
 
     steps = args.steps or DEFAULT_STEPS["batch_sweep"]
     sweep = W.batch_sweep(storage=args.storage)
-    members = [(w["spec"], w["body"]) for w in sweep]
+    members = [(dict(w["spec"], offset_ref=args.offset_ref), w["body"]) for w in sweep]
     nodes = sum(s["nx"] * s["ny"] for s, _ in members)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -351,7 +354,8 @@ def run_single(args):
     wl = {"free_viv": W.free_viv, "sedimentation": W.sedimentation,
           "roofline": W.roofline_grid}[args.workload](storage=args.storage)
     spec = dict(wl["spec"], rows_per_tile=args.rows, store_mode=args.store,
-                tile_width=args.tile_width, layout=args.layout, finalize=args.finalize)
+                tile_width=args.tile_width, layout=args.layout, finalize=args.finalize,
+                offset_ref=args.offset_ref)
     nodes = spec["nx"] * spec["ny"]
     if args.copy_calibration:
         copy_calibration()
