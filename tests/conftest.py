@@ -1,3 +1,4 @@
+import contextlib
 import os
 import sys
 
@@ -11,6 +12,19 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
     config.addinivalue_line("markers", "slow: CPU test that takes tens of seconds")
+
+
+@contextlib.contextmanager
+def torch_threads(n):
+    """Run a block with n torch CPU threads (the reverse-mode oracle works on grids of a
+    few thousand nodes, which one thread finishes several times faster than a pool)."""
+    import torch
+    old = torch.get_num_threads()
+    torch.set_num_threads(n)
+    try:
+        yield
+    finally:
+        torch.set_num_threads(old)
 
 
 @pytest.fixture(scope="session")

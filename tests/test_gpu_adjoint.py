@@ -10,6 +10,7 @@ import sys
 
 import numpy as np
 import pytest
+from conftest import torch_threads
 
 from paper_1905_05110_amd import workloads as W
 
@@ -95,7 +96,8 @@ def test_reduced_drag_copy_against_the_oracle(gpu):
     steps = 400
     w = (1.0 / (steps * 0.5 * wl["U0"] ** 2 * wl["D"]), 0.0)
     _flush("adjoint 128x64 vs oracle")
-    ref = ado.Mirror(wl["spec"], wl["body"]).gradient(steps, 100, w)
+    with torch_threads(1):
+        ref = ado.Mirror(wl["spec"], wl["body"]).gradient(steps, 100, w)
     adj, g = run_gpu(gpu, wl["spec"], wl["body"], steps, 100, w)
     _flush("errors %s" % (compare(g, ref),))
     adj.close()
