@@ -916,7 +916,7 @@ template <class S, int ROWS, bool NT, bool PART, int TW>
 __device__ __forceinline__ void step_rows(const SimDesc& d,
                                           const TileScalars<typename Codec<S>::T>& c, int tx,
                                           int ty, double acc[NRED], const double* pose,
-                                          typename Codec<S>::T g[NQ]) {
+                                          typename Codec<S>::T g[NQ], bool& hit) {
     using T = typename Codec<S>::T;
     const char* fin = c.fin;
     char* fout = c.fout;
@@ -965,6 +965,7 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
                     }
                 }
                 if (chi != 0.0) {
+                    hit = true;
                     collide<T, true>(c, g, (T)chi, (T)dsx, (T)dsy, out, o);
                     const double dFx = (double)o.dFx, dFy = (double)o.dFy;
                     const double jx = (double)o.jgx + d.u0x, jy = (double)o.jgy + d.u0y;
@@ -1271,7 +1272,8 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     const bool part = tx >= bx0 && tx <= bx1 && ty >= by0 && ty <= by1;
     double acc[NRED];
     if (!part) {
-        step_rows<S, ROWS, NT, false, TW>(d, ts, tx, ty, acc, nullptr, g);
+        bool unused = false;
+        step_rows<S, ROWS, NT, false, TW>(d, ts, tx, ty, acc, nullptr, g, unused);
         return;  // uniform over the workgroup
     }
     const bool writer = tx == bx0 && ty == by0;
@@ -1292,13 +1294,20 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     }
 #pragma unroll
     for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
-    step_rows<S, ROWS, NT, true, TW>(d, ts, tx, ty, acc, pose, g);
+    bool hit = false;  // a node of this lane lies in the body (chi != 0)
+    step_rows<S, ROWS, NT, true, TW>(d, ts, tx, ty, acc, pose, g, hit);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // A wave none of whose nodes lies in the body holds +0 in every accumulator, whose
+    // sum is +0: it skips the cross-lane sums (most waves of a tile meeting a small body).
+    if (__any(hit)) {  // uniform over the wave
 #pragma unroll
-    for (int k = 0; k < NRED - 3; ++k) {
-        const double s = wave_sum(acc[k]);
-        if (lane == 0) red[wave][k] = s;
+        for (int k = 0; k < NRED - 3; ++k) {
+            const double s = wave_sum(acc[k]);
+            if (lane == 0) red[wave][k] = s;
+        }
+    } else if (lane < NRED - 3) {
+        red[wave][lane] = 0.0;
     }
     // the momentum-exchange pass runs once the other sums have left the registers
     if (B.mem) {  // uniform

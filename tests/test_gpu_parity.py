@@ -497,6 +497,34 @@ def test_full_size_free_viv_first_steps(gpu, storage):
     g.close()
 
 
+def test_full_size_sedimentation_first_steps(gpu):
+    """The 1024x4096 closed box with its free falling disc (FP32 storage), in the launch
+    configuration the benchmark picks for it (one row and 512 columns per tile, plain
+    stores, body state finalized in the tiles): 10 steps from a seeded near-rest state
+    against the FP64 oracle."""
+    from oracle import oracle as orc
+    wl = W.sedimentation(storage="fp32")
+    spec = dict(wl["spec"], rows_per_tile=1, store_mode="plain", tile_width=512,
+                finalize="tiles")
+    _flush("full size sedimentation fp32")
+    f0 = W.random_populations(spec["nx"], spec["ny"], seed=2024, amp=0.02)
+    o = orc.OracleSim(wl["spec"], wl["body"])
+    g = gpu.Sim(spec, wl["body"], graph_steps=2)
+    o.set_populations(f0)
+    g.set_populations(f0)
+    ro = o.step(10)
+    g.step(10)
+    rg = g.forces()
+    e = rel(g.get_populations(), o.get_populations())
+    ef = rel(rg["fvp"], ro["fvp"])
+    eq = np.abs(rg["q"] - ro["q"]).max()
+    _flush("sedimentation: population err %.2e, force err %.2e, pose err %.2e (moved %.2e)"
+           % (e, ef, eq, np.abs(ro["q"][-1] - ro["q"][0]).max()))
+    moved = np.abs(ro["q"][-1] - ro["q"][0]).max()
+    assert e <= 1e-6 and ef <= 1e-4 and eq <= 1e-4 * moved + 1e-12
+    g.close()
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
 def test_launch_configurations_agree(gpu, storage):
     """Rows and columns per tile and store instructions change the schedule, not the method: the
