@@ -67,7 +67,7 @@ def parse():
                     help="steps per captured HIP graph in the timed region (0: eager launches)")
     ap.add_argument("--rows", type=int, default=0, help="rows per tile (0: autotune)")
     ap.add_argument("--store", default="auto", choices=("auto", "plain", "nontemporal"))
-    ap.add_argument("--tile-width", type=int, default=0, choices=(0, 256, 512),
+    ap.add_argument("--tile-width", type=int, default=0, choices=(0, 64, 256, 512),
                     help="columns per tile (0: autotune)")
     ap.add_argument("--order", default="auto",
                     choices=("auto", "given", "largest_first", "interleaved"),

@@ -150,7 +150,7 @@ typedef struct {
     int fp16_scale_log2;   /* k of the FP16 offset scale 2^k, 0..14 (default 10) */
     int history_cap;       /* force records kept on the device between drains (default 65536) */
     int offset_ref;        /* LBM_REF_AUTO (default), LBM_REF_INITIAL or LBM_REF_REST */
-    int rows_per_tile;     /* grid rows per tile (nodes per lane): 1, 2, 4;
+    int rows_per_tile;     /* grid rows per lane of the step kernel: 1, 2, 4;
                               0 = default (1).  Each setting is deterministic; results of
                               different settings agree to rounding (kernel variants may
                               contract multiply-adds differently; FP64 force sums follow
@@ -159,10 +159,15 @@ typedef struct {
     void* hip_stream;      /* hipStream_t to run on; NULL: the library creates one */
     void* pop_buffers[2];  /* optional caller-owned device buffers of lbm_pop_bytes() each */
     int collision;         /* LBM_COLLIDE_MRT (default) or LBM_COLLIDE_BGK */
-    int tile_width;        /* grid columns per tile (threads per workgroup of the step
-                              kernel): 0 = default (256), 256 or 512.  Like rows_per_tile
-                              a launch choice: results of different settings agree to
-                              rounding (the FP64 force sums follow the tile order). */
+    int tile_width;        /* grid columns per tile of the step kernel: 0 = default
+                              (256), 64, 256 or 512.  A tile of 256 or 512 columns is one
+                              workgroup of as many threads, rows_per_tile rows high; a
+                              tile of 64 columns is a 256-thread workgroup whose four
+                              waves take four consecutive row groups, 4 rows_per_tile
+                              rows high (narrow or ragged grids leave fewer idle lanes).
+                              Like rows_per_tile a launch choice: results of different
+                              settings agree to rounding (the FP64 force sums follow the
+                              tile order). */
     int layout;            /* LBM_LAYOUT_AUTO (default), _ROWS or _PLANES */
     int finalize;          /* LBM_FINALIZE_AUTO (default), _TILES or _KERNEL */
 } lbm_opts;
@@ -280,7 +285,7 @@ int64_t lbm_step_index(const lbm_sim* sim);
 int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms);
 
 /* Chooses the launch configuration of the step kernel (rows per tile 1/2/4, plain or
- * nontemporal stores, 256 or 512 columns per tile and, with a body, how its state is
+ * nontemporal stores, 64, 256 or 512 columns per tile and, with a body, how its state is
  * finalized) by timing each candidate on a scratch simulation of the same grid, storage
  * and body, started from a copy of sim's current populations and outflow memory (call it
  * once the flow has developed: the uniform start state is exactly zero in offsets and
@@ -339,7 +344,7 @@ typedef struct {
     int store_mode;     /* LBM_STORE_* */
     int order;          /* LBM_ORDER_* */
     void* hip_stream;   /* NULL: the library creates one */
-    int tile_width;     /* 0 (default: 256), 256 or 512 */
+    int tile_width;     /* 0 (default: 256), 64, 256 or 512 (see lbm_opts) */
     int layout;         /* LBM_LAYOUT_AUTO: each member's own opts->layout; else every
                            member takes this one */
     int finalize;       /* LBM_FINALIZE_AUTO: each member's own opts->finalize; else every

@@ -245,7 +245,7 @@ int enqueue_recompute(lbm_adjoint* A, int store, hipStream_t st) {
     const long long words = (long long)(s->pop_bytes / 4);
     const int blocks = (int)std::min<long long>(4096, (words + 255) / 256);
     hipLaunchKernelGGL(k_adj_load_segment, dim3(blocks), dim3(256), 0, st, A->ad_d + store);
-    const dim3 fgrid(s->desc.tiles_x, s->desc.tiles_y);
+    const dim3 fgrid = step_grid(s->desc);
     const SimDesc* sd = A->seg_descs_d + (size_t)store * A->K;
     dispatch(A->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
@@ -695,7 +695,7 @@ int lbm_adjoint_time_kernels(lbm_adjoint* A, int reps, double* adjoint_us, doubl
     lbm_sim* s = A->sim;
     hipEvent_t e[3];
     for (auto& x : e) AHIP_TRY(A, hipEventCreate(&x));
-    const dim3 fgrid(s->desc.tiles_x, s->desc.tiles_y), agrid(A->atx, A->ny);
+    const dim3 fgrid = step_grid(s->desc), agrid(A->atx, A->ny);
     AHIP_TRY(A, hipEventRecord(e[0], s->stream));
     dispatch(A->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;

@@ -99,7 +99,7 @@ static void update_finalize(lbm_sim* s) {
         } else if (s->fin_req == LBM_FINALIZE_AUTO) {
             const BodyState& st = s->body_h.st[s->host_step & 1];
             int box[4];
-            body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, s->body_h, st.q[0], st.q[1], box);
+            body_tiles(s->nx, s->ny, s->desc.rows, s->desc.tile_w, s->body_h, st.q[0], st.q[1], box);
             k = box_count(box) > FINALIZE_TILES_MAX;
         }
     }
@@ -115,7 +115,7 @@ static void update_finalize(lbm_sim* s) {
 static int launch_step(lbm_sim* s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                        SlotArray sa = SlotArray{nullptr, 0}) {
     const int p = (int)(s->host_step & 1);
-    const dim3 grid(s->desc.tiles_x, s->desc.tiles_y);
+    const dim3 grid = step_grid(s->desc);
     if (ev0) HIP_TRY(s, hipEventRecord(ev0, s->stream));
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
@@ -217,8 +217,9 @@ static int check_opts(int nx, int ny, lbm_rates r, double eta, const lbm_opts& o
     if (o.rows_per_tile != 0 && o.rows_per_tile != 1 && o.rows_per_tile != 2 &&
         o.rows_per_tile != 4)
         return m = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
-    if (o.tile_width != 0 && o.tile_width != TILE_X && o.tile_width != TILE_WIDE)
-        return m = "tile_width must be 0, 256 or 512", LBM_ERR_ARG;
+    if (o.tile_width != 0 && o.tile_width != TILE_NARROW && o.tile_width != TILE_X &&
+        o.tile_width != TILE_WIDE)
+        return m = "tile_width must be 0, 64, 256 or 512", LBM_ERR_ARG;
     if (o.collision != LBM_COLLIDE_MRT && o.collision != LBM_COLLIDE_BGK)
         return m = "collision must be LBM_COLLIDE_MRT or LBM_COLLIDE_BGK", LBM_ERR_ARG;
     if (o.store_mode < LBM_STORE_AUTO || o.store_mode > LBM_STORE_NONTEMPORAL)
@@ -314,9 +315,14 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     s->nt = o.store_mode == LBM_STORE_NONTEMPORAL ||
             (o.store_mode == LBM_STORE_AUTO && 2 * s->pop_bytes > (size_t(1) << 30));
     const int tile_w = o.tile_width ? o.tile_width : TILE_X;
+    const int tile_h = s->rows * tile_stack(tile_w);
     const int tiles_x = (nx + tile_w - 1) / tile_w;
-    const int tiles_y = (ny + s->rows - 1) / s->rows;
-    const int ntiles = (nx + TILE_X - 1) / TILE_X * ny;  // enough slots for any tile shape
+    const int tiles_y = (ny + tile_h - 1) / tile_h;
+    // enough slots for any tile shape: one-row tiles of TILE_X columns, or the four-row
+    // tiles of TILE_NARROW columns (more of them than of the former on grids of three rows)
+    const long long ntiles = std::max((long long)((nx + TILE_X - 1) / TILE_X) * ny,
+                                      (long long)((nx + TILE_NARROW - 1) / TILE_NARROW) *
+                                          ((ny + 3) / 4));
     CREATE_TRY(hipMalloc(&s->outlet, 3 * (size_t)ny * tsz));
     CREATE_TRY(hipMalloc((void**)&s->body_d, sizeof(BodyDev)));
     CREATE_TRY(hipMalloc((void**)&s->partials, 2 * (size_t)ntiles * NRED * sizeof(double)));
@@ -332,7 +338,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.outlet_out = s->outlet;
     d.body = s->body_d;
     d.partials = s->partials;
-    d.part_stride = (long long)ntiles * NRED;
+    d.part_stride = ntiles * NRED;
     d.hist = s->hist;
     d.flag = s->flag;
     {
@@ -342,7 +348,7 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     d.fpitch = row_pitch(nx);
     d.nx = nx;
     d.ny = ny;
-    d.rows = s->rows;
+    d.rows = tile_h;
     d.tiles_x = tiles_x;
     d.tile_w = tile_w;
     d.tiles_y = tiles_y;
@@ -553,7 +559,7 @@ int lbm_set_body(lbm_sim* s, const lbm_body* b) {
     st.step = s->host_step;
     st.pin_valid = 0;
     st.fresh = 1;
-    body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, B, q[0], q[1], st.boxM);
+    body_tiles(s->nx, s->ny, s->desc.rows, s->desc.tile_w, B, q[0], q[1], st.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = st.boxM[k];
     // a step takes part by the box of the state before it: the other slot starts as a
     // copy of this one
@@ -661,7 +667,7 @@ int lbm_step_static(lbm_sim* s, int64_t n) {
         // spans at most one more tile each way than that of the pose set last
         const BodyState& st = s->body_h.st[s->host_step & 1];
         int box[4];
-        body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, s->body_h, st.q[0], st.q[1], box);
+        body_tiles(s->nx, s->ny, s->desc.rows, s->desc.tile_w, s->body_h, st.q[0], st.q[1], box);
         const long long need = (long long)(box[1] - box[0] + 3) * (box[3] - box[2] + 3) * NRED;
         if (need > STATIC_SLOT_DOUBLES / 2)
             return fail(s, LBM_ERR_ARG, "the body's tiles need more partial slots than the static array holds (" +
@@ -802,10 +808,11 @@ int lbm_get_body_state(lbm_sim* s, double* q, double* v) {
 static int apply_launch_config(lbm_sim* s, int rows, bool nt, int tile_w) {
     int rc0 = sync_check(s);  // the next step's state is then fresh
     if (rc0 && rc0 != LBM_ERR_UNSTABLE) return rc0;
+    const int tile_h = rows * tile_stack(tile_w);
     s->rows = rows;
     s->nt = nt;
-    s->desc.rows = rows;
-    s->desc.tiles_y = (s->ny + rows - 1) / rows;
+    s->desc.rows = tile_h;
+    s->desc.tiles_y = (s->ny + tile_h - 1) / tile_h;
     s->desc.tile_w = tile_w;
     s->desc.tiles_x = (s->nx + tile_w - 1) / tile_w;
     BodyDev B;
@@ -814,8 +821,8 @@ static int apply_launch_config(lbm_sim* s, int rows, bool nt, int tile_w) {
     // part), in the new tiles
     BodyState& st = B.st[s->host_step & 1];
     BodyState& before = B.st[(s->host_step & 1) ^ 1];
-    body_tiles(s->nx, s->ny, rows, tile_w, B, st.q[0], st.q[1], st.boxM);
-    body_tiles(s->nx, s->ny, rows, tile_w, B, before.q[0], before.q[1], before.boxM);
+    body_tiles(s->nx, s->ny, tile_h, tile_w, B, st.q[0], st.q[1], st.boxM);
+    body_tiles(s->nx, s->ny, tile_h, tile_w, B, before.q[0], before.q[1], before.boxM);
     for (int k = 0; k < 4; ++k) st.part_box[k] = before.boxM[k];
     s->row_shift = dispatch_row_shift(s, st.boxM);
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(B), hipMemcpyHostToDevice));
@@ -866,7 +873,8 @@ static bool tune_lookup(const char* path, const std::string& key, int& rows, int
         const char* fp = std::strstr(line, "\"fin\": ");
         if (fp && std::sscanf(fp, "\"fin\": %d", &fm) != 1) fm = LBM_FINALIZE_AUTO;
         if (key == k && (r == 1 || r == 2 || r == 4) && (n == 0 || n == 1) &&
-            (w == TILE_X || w == TILE_WIDE) && fm >= LBM_FINALIZE_AUTO && fm <= LBM_FINALIZE_KERNEL) {
+            (w == TILE_NARROW || w == TILE_X || w == TILE_WIDE) && fm >= LBM_FINALIZE_AUTO &&
+            fm <= LBM_FINALIZE_KERNEL) {
             rows = r;
             nt = n;
             tile_w = w;
@@ -892,12 +900,12 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
         const int cur = (int)(s->host_step & 1);
         const size_t outlet_bytes = 3 * (size_t)s->ny * (s->storage == LBM_FP64 ? 8 : 4);
         const int cand_rows[3] = {1, 2, 4};
-        const int cand_w[2] = {TILE_X, TILE_WIDE};
+        const int cand_w[3] = {TILE_NARROW, TILE_X, TILE_WIDE};
         // with a body, both ways of finalizing its state are timed
         const int cand_fin[2] = {LBM_FINALIZE_TILES, LBM_FINALIZE_KERNEL};
-        const int ncand = s->has_body ? 24 : 12;
+        const int ncand = s->has_body ? 36 : 18;
         for (int cj = 0; cj < ncand; ++cj) {
-            const int ci = cj % 12;
+            const int ci = cj % 18;
             lbm_opts o = s->opts;
             o.hip_stream = nullptr;
             o.pop_buffers[0] = o.pop_buffers[1] = nullptr;
@@ -905,7 +913,7 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
             o.rows_per_tile = cand_rows[(ci / 2) % 3];
             o.store_mode = (ci & 1) ? LBM_STORE_NONTEMPORAL : LBM_STORE_PLAIN;
             o.tile_width = cand_w[ci / 6];
-            o.finalize = s->has_body ? cand_fin[cj / 12] : s->fin_req;
+            o.finalize = s->has_body ? cand_fin[cj / 18] : s->fin_req;
             lbm_sim* t = nullptr;
             int rc = lbm_create(s->nx, s->ny, s->rates, s->eta, &o, &t);
             if (rc) return fail(s, rc, std::string("autotune: ") + lbm_last_error(nullptr));
@@ -943,7 +951,7 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
                 rows = cand_rows[(ci / 2) % 3];
                 nt = ci & 1;
                 tile_w = cand_w[ci / 6];
-                fin = s->has_body ? cand_fin[cj / 12] : LBM_FINALIZE_AUTO;
+                fin = s->has_body ? cand_fin[cj / 18] : LBM_FINALIZE_AUTO;
             }
         }
         if (cache_path) {
@@ -1057,8 +1065,8 @@ int lbm_load(lbm_sim* s, const void* buf, size_t size) {
     BodyState& st = B.st[s->host_step & 1];
     BodyState& before = B.st[(s->host_step & 1) ^ 1];
     if (st.fresh && B.active) {
-        body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, B, st.q[0], st.q[1], st.boxM);
-        body_tiles(s->nx, s->ny, s->rows, s->desc.tile_w, B, before.q[0], before.q[1], before.boxM);
+        body_tiles(s->nx, s->ny, s->desc.rows, s->desc.tile_w, B, st.q[0], st.q[1], st.boxM);
+        body_tiles(s->nx, s->ny, s->desc.rows, s->desc.tile_w, B, before.q[0], before.q[1], before.boxM);
         for (int k = 0; k < 4; ++k) st.part_box[k] = before.boxM[k];
     }
     HIP_TRY(s, hipMemcpy(s->body_d, &B, sizeof(BodyDev), hipMemcpyHostToDevice));
@@ -1135,6 +1143,44 @@ static std::vector<int2> batch_schedule(const lbm_batch* b, int order) {
     if (order == LBM_ORDER_LARGEST_FIRST)
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return tiles(a) > tiles(c); });
     std::vector<int2> out;
+    if (b->tile_w == TILE_NARROW) {
+        // The tile rows of every simulation, in the chosen order (each simulation's rows
+        // rotated to put its body's rows early, as below), are dealt out to eight queues,
+        // each row whole to the queue holding the fewest tiles so far; entry 8 k + x of
+        // the schedule is the k-th tile of queue x.  Workgroup 8 k + x runs on XCD x, so
+        // horizontally adjacent tiles, which share the cache lines their x-shifted pulls
+        // straddle, run one after the other on one XCD.  Where a queue has run out, the
+        // entry is a gap (simulation -1).
+        std::vector<std::pair<int, int>> rows;  // (simulation, tile row)
+        if (order == LBM_ORDER_INTERLEAVED) {
+            int maxr = 0;
+            for (int i = 0; i < b->n; ++i) maxr = std::max(maxr, b->sims[i]->desc.tiles_y);
+            for (int r = 0; r < maxr; ++r)
+                for (int i = 0; i < b->n; ++i)
+                    if (r < b->sims[i]->desc.tiles_y) rows.emplace_back(i, r);
+        } else {
+            for (int i : idx) {
+                const int ty = b->sims[i]->desc.tiles_y;
+                for (int r0 = 0; r0 < ty; ++r0)
+                    rows.emplace_back(i, (r0 + b->sims[i]->row_shift) % ty);
+            }
+        }
+        std::vector<int2> q[8];
+        for (const auto& rw : rows) {
+            int x = 0;
+            for (int k = 1; k < 8; ++k)
+                if (q[k].size() < q[x].size()) x = k;
+            for (int c = 0; c < b->sims[rw.first]->desc.tiles_x; ++c)
+                q[x].push_back(make_int2(rw.first, (rw.second << 16) | c));
+        }
+        size_t len = 0;
+        for (const auto& v : q) len = std::max(len, v.size());
+        out.assign(8 * len, make_int2(-1, 0));
+        for (int x = 0; x < 8; ++x)
+            for (size_t k = 0; k < q[x].size(); ++k) out[8 * k + x] = q[x][k];
+        while (!out.empty() && out.back().x < 0) out.pop_back();
+        return out;
+    }
     if (order == LBM_ORDER_INTERLEAVED) {
         // one row of tiles from each simulation in turn
         int maxr = 0;
@@ -1253,8 +1299,9 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
         return g_batch_create_error = "unknown storage", LBM_ERR_ARG;
     if (bo.rows_per_tile != 0 && bo.rows_per_tile != 1 && bo.rows_per_tile != 2 && bo.rows_per_tile != 4)
         return g_batch_create_error = "rows_per_tile must be 0, 1, 2 or 4", LBM_ERR_ARG;
-    if (bo.tile_width != 0 && bo.tile_width != TILE_X && bo.tile_width != TILE_WIDE)
-        return g_batch_create_error = "tile_width must be 0, 256 or 512", LBM_ERR_ARG;
+    if (bo.tile_width != 0 && bo.tile_width != TILE_NARROW && bo.tile_width != TILE_X &&
+        bo.tile_width != TILE_WIDE)
+        return g_batch_create_error = "tile_width must be 0, 64, 256 or 512", LBM_ERR_ARG;
     if (bo.layout < LBM_LAYOUT_AUTO || bo.layout > LBM_LAYOUT_PLANES)
         return g_batch_create_error = "unknown layout", LBM_ERR_ARG;
     if (bo.finalize < LBM_FINALIZE_AUTO || bo.finalize > LBM_FINALIZE_KERNEL)
@@ -1308,7 +1355,8 @@ int lbm_batch_create(int n, const lbm_batch_desc* descs, const lbm_batch_opts* o
             rc = lbm_set_body(s, descs[i].body);
             if (rc) return b->err = "simulation " + std::to_string(i) + ": " + s->err, bail(rc);
         }
-        if (s->desc.tiles_x > 0xffff || s->desc.tiles_y > 0x7fff)
+        // schedule entries hold 16-bit tile coordinates, in every tile shape
+        if ((s->nx + TILE_NARROW - 1) / TILE_NARROW > 0xffff || s->ny > 0x7fff)
             return b->err = "grid too large for a batch", bail(LBM_ERR_ARG);
     }
     // one launch configuration for the whole batch; the defaults follow the single-grid
@@ -1500,19 +1548,19 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* rows_out, int* nt_out
     bool best_nt = false;
     double best = -1.0, us = 0.0;
     const int cand_rows[3] = {1, 2, 4};
-    const int cand_w[2] = {TILE_X, TILE_WIDE};
+    const int cand_w[3] = {TILE_NARROW, TILE_X, TILE_WIDE};
     // two passes over the candidates, each keeping its faster pass: the first candidates
     // of a single pass run while the device is still reaching its working clocks
-    double cand_us[12];
+    double cand_us[18];
     for (int pass = 0; pass < 2; ++pass)
-        for (int ci = 0; ci < 12; ++ci) {
+        for (int ci = 0; ci < 18; ++ci) {
             const int rows = cand_rows[(ci / 2) % 3], w = cand_w[ci / 6];
             int rc = batch_time(b, rows, ci & 1, LBM_ORDER_LARGEST_FIRST, w, LBM_FINALIZE_AUTO,
                                 trial_steps, us);
             if (rc) return rc;
             cand_us[ci] = pass == 0 ? us : std::min(cand_us[ci], us);
         }
-    for (int ci = 0; ci < 12; ++ci)
+    for (int ci = 0; ci < 18; ++ci)
         if (best < 0 || cand_us[ci] < best) {
             best = cand_us[ci];
             best_rows = cand_rows[(ci / 2) % 3];

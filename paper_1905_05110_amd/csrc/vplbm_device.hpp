@@ -18,12 +18,20 @@
 namespace vplbm {
 
 constexpr int NQ = 9;
-// A tile is TW columns (one per lane of a TW-thread workgroup) x ROWS rows; the step
-// kernel is built for TW = TILE_X and TILE_WIDE, chosen per launch.  TILE_X is also the
-// width of the adjoint's tiles and the workgroup size of the body-state sums.
+// A tile is TW columns; the step kernel is built for TW = TILE_NARROW, TILE_X and
+// TILE_WIDE, chosen per launch.  With TW = TILE_X or TILE_WIDE a tile is one row of TW
+// columns per row of a TW-thread workgroup (each lane walks ROWS rows down its column);
+// with TW = TILE_NARROW the TILE_X-thread workgroup stacks its four waves, one per row,
+// so that a tile is 64 columns x 4 ROWS rows: a row's ragged end then leaves at most
+// part of one wave idle, not whole waves of a wide tile.  TILE_X is also the width of
+// the adjoint's tiles and the workgroup size of the body-state sums.
+constexpr int TILE_NARROW = 64;
 constexpr int TILE_X = 256;
 constexpr int TILE_WIDE = 512;
 constexpr int NWAVE = TILE_X / 64;
+// threads of the step kernel's workgroup, and its rows of lanes, for tiles TW wide
+__host__ __device__ constexpr int tile_lanes(int tw) { return tw == TILE_NARROW ? TILE_X : tw; }
+__host__ __device__ constexpr int tile_stack(int tw) { return tile_lanes(tw) / tw; }
 // per-step FP64 sums: penalization force (2) and torque (1); momentum inside the body
 // after collision (2 + 1 angular) and before it (2 + 1); momentum-exchange force (2)
 // and torque (1)
@@ -136,8 +144,9 @@ struct SimDesc {
     int pitch;           // stride between two rows of one direction's populations (elements)
     int fpitch;          // row stride of a single-field array such as dJ/dchi (elements)
     int layout;          // LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES (pitch and ps follow from it)
-    int rows, tiles_x, tiles_y, hist_cap;
-    int tile_w;          // columns per tile of the step kernel: TILE_X or TILE_WIDE
+    int rows;            // rows per tile: rows per lane x the workgroup's rows of lanes
+    int tiles_x, tiles_y, hist_cap;
+    int tile_w;          // columns per tile of the step kernel: TILE_NARROW, TILE_X or TILE_WIDE
     int bc[4];
     // x-edge rule (west, east) for the three directions whose source lies outside (1, 5, 8
     // at the west side, 3, 6, 7 at the east): source (i + dx, j + dy) and its plane
@@ -892,12 +901,22 @@ __device__ __forceinline__ void pull_wave_edge(const SimDesc& d,
 // penalized, collided and stored.  PART tiles (those meeting the body) also rasterise
 // chi and u_s and accumulate force, torque and internal momentum in FP64.
 // First row of a tile: the pulled offsets of node (i, j0), interior or edge.
-template <class S, int TW>
+template <int TW, int ROWS>
+__device__ __forceinline__ void tile_node(int tx, int ty, int& i, int& j0) {
+    // column of this lane and first of its ROWS rows in tile (tx, ty)
+    constexpr int K = tile_stack(TW);
+    const int col = K == 1 ? (int)threadIdx.x : (int)(threadIdx.x & (TW - 1));
+    const int grp = K == 1 ? 0 : (int)(threadIdx.x / TW);  // one wave per row group
+    i = tx * TW + col;
+    j0 = (ty * K + grp) * ROWS;
+}
+
+template <class S, int ROWS, int TW>
 __device__ __forceinline__ void pull_first(const SimDesc& d,
                                            const TileScalars<typename Codec<S>::T>& ts, int tx,
-                                           int ty, int rows, typename Codec<S>::T g[NQ]) {
-    const int i = tx * TW + (int)threadIdx.x;
-    const int j0 = ty * rows;
+                                           int ty, typename Codec<S>::T g[NQ]) {
+    int i, j0;
+    tile_node<TW, ROWS>(tx, ty, i, j0);
     // a wave with any edge node takes the boundary-rule pull for all its lanes (it
     // handles interior nodes too): one path and one round of loads per wave
     const bool inner = i >= 1 && i <= ts.nx - 2 && j0 >= 1 && j0 <= ts.ny - 2;
@@ -920,8 +939,8 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
     using T = typename Codec<S>::T;
     const char* fin = c.fin;
     char* fout = c.fout;
-    const int i = tx * TW + (int)threadIdx.x;
-    const int j0 = ty * ROWS;
+    int i, j0;
+    tile_node<TW, ROWS>(tx, ty, i, j0);
     const int nx = c.nx, ny = c.ny;
     const bool col_ok = i < nx;
     const bool col_inner = i >= 1 && i <= nx - 2;
@@ -940,7 +959,7 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int j = j0 + r;
-        if (j >= ny) break;  // uniform over the workgroup
+        if (j >= ny) break;  // uniform over the wave
         if (r + 1 < ROWS && j + 1 < ny) {  // uniform
             if (__all(col_inner && j + 1 <= ny - 2))
                 pull_interior<S>(P, ((unsigned)(j + 1) * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S),
@@ -1014,7 +1033,8 @@ template <class S, int ROWS, int TW>
 __device__ __forceinline__ void mem_pass(const SimDesc& d, int tx, int ty, int p,
                                          const double* pose, double m[3]) {
     const BodyDev& B = *d.body;
-    const int i = tx * TW + (int)threadIdx.x;
+    int i, j0;
+    tile_node<TW, ROWS>(tx, ty, i, j0);
     m[0] = m[1] = m[2] = 0.0;
     if (!B.active || !B.mem || i >= d.nx) return;
     // uniform over the workgroup: kept in scalar registers
@@ -1026,7 +1046,7 @@ __device__ __forceinline__ void mem_pass(const SimDesc& d, int tx, int ty, int p
     double mx = 0.0, my = 0.0, mt = 0.0;
 #pragma unroll 1
     for (int r = 0; r < ROWS; ++r) {
-        const int j = ty * ROWS + r;
+        const int j = j0 + r;
         if (j >= d.ny) break;
         const double rx = (double)i - X, ry = (double)j - Y;
         const double d2 = disc_d2(rx, ry);
@@ -1232,7 +1252,8 @@ __device__ __forceinline__ double* slot_base(const SimDesc& d, SlotArray sa, int
 template <class S, int ROWS, bool NT, int TW>
 __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int p, SlotArray sa) {
     using T = typename Codec<S>::T;
-    __shared__ double red[TW / 64][NRED];
+    constexpr int NW = tile_lanes(TW) / 64;  // waves of the workgroup
+    __shared__ double red[NW][NRED];
     __shared__ double pose_set[6];
     __shared__ BodyStep bs;
     BodyDev& B = *d.body;
@@ -1260,7 +1281,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
 #pragma unroll
     for (int k = 0; k < 4; ++k) box_q[k] = __builtin_amdgcn_raw_buffer_load_b32(bst, sq + o_box + 4 * k, 0, 0);
     T g[NQ];
-    pull_first<S, TW>(d, ts, tx, ty, ROWS, g);
+    pull_first<S, ROWS, TW>(d, ts, tx, ty, g);
     const int fresh = __builtin_amdgcn_readfirstlane(fresh_v);
     // the tiles that take part: the box of the previous step's pose (with a margin that
     // covers this step's), whether this step's state is derived or was made final by a
@@ -1325,7 +1346,7 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     if (threadIdx.x < NRED) {
         const int k = threadIdx.x;
         double s = red[0][k];
-        for (int w = 1; w < TW / 64; ++w) s += red[w][k];
+        for (int w = 1; w < NW; ++w) s += red[w][k];
         const int slot = (ty - by0) * (bx1 - bx0 + 1) + (tx - bx0);
         slot_base(d, sa, p)[(long long)slot * NRED + k] = s;
     }

@@ -13,10 +13,11 @@ namespace vplbm {
 // _Float16, bf16s), each defined in its own translation unit.
 template <class S>
 struct Launch {
-    // the kernel of one time step (parity p; rows per tile 1, 2 or 4; nt selects
-    // nontemporal stores; tile_w columns per tile, TILE_X or TILE_WIDE; tile rows
-    // dispatched from row_shift on, 0 <= row_shift < grid.y; the partial force slots in
-    // sa.slots when that is set, else in the simulation's own array)
+    // the kernel of one time step (parity p; rows per lane 1, 2 or 4; nt selects
+    // nontemporal stores; tile_w columns per tile, TILE_NARROW, TILE_X or TILE_WIDE;
+    // grid from step_grid; tile rows dispatched from row_shift on, 0 <= row_shift <
+    // tiles_y; the partial force slots in sa.slots when that is set, else in the
+    // simulation's own array)
     static void step(const SimDesc* dd, dim3 grid, int rows, bool nt, int tile_w, int p,
                      hipStream_t st, int row_shift = 0, SlotArray sa = SlotArray{nullptr, 0});
     // one time step of several simulations in one launch: workgroup b handles the tile
@@ -30,17 +31,33 @@ struct Launch {
 };
 
 // ---------------------------------------------------------------------------------
-// One kernel serves a single simulation (sched == nullptr, 2D grid of its tiles, tile
-// row (blockIdx.y + row_shift) mod tiles_y, tile column (blockIdx.x + blockIdx.y) mod
-// tiles_x) and a batch (1D grid over sched, whose order the host chooses).  The tile body has a single call site, so a simulation
-// computes bitwise the same inside a batch as alone.
+// Grid of the step kernel for a single simulation.  Tiles of TILE_X or TILE_WIDE
+// columns: tiles_x x tiles_y workgroups.  TILE_NARROW tiles: 8 tiles_x x ceil(tiles_y / 8)
+// workgroups, see k_step.
+inline dim3 step_grid(const SimDesc& d) {
+    if (d.tile_w == TILE_NARROW) return dim3(8 * d.tiles_x, (d.tiles_y + 7) / 8);
+    return dim3(d.tiles_x, d.tiles_y);
+}
+
+// One kernel serves a single simulation (sched == nullptr) and a batch (1D grid over
+// sched, whose order the host chooses; an entry with a negative simulation index is a
+// gap and does nothing).  The tile body has a single call site, so a simulation computes
+// bitwise the same inside a batch as alone.  Consecutive workgroups go to the eight XCDs
+// in turn.  A single simulation with wide tiles (2D grid of its tiles) takes tile row
+// (blockIdx.y + row_shift) mod tiles_y and tile column (blockIdx.x + blockIdx.y) mod
+// tiles_x: skewing the column by the row spreads each column, and so the longer work of
+// the body's tiles, over all XCDs instead of one or two.  With narrow tiles, XCD x walks
+// the tile rows x, x + 8, x + 16, ... (before the rotation by row_shift), each from left
+// to right: horizontally adjacent tiles, which share the cache lines their x-shifted
+// pulls straddle, run one after the other on one XCD, and every XCD meets the body's
+// rows.
 // Single-row tiles of 4-byte or narrower storage fit in 64 registers without spilling:
 // eight waves per SIMD then hide more memory latency.
 template <class S, int ROWS>
 constexpr int step_waves() { return (sizeof(S) <= 4 && ROWS == 1) ? 8 : 1; }
 
 template <class S, int ROWS, bool NT, int TW>
-__global__ __launch_bounds__(TW) __attribute__((amdgpu_waves_per_eu(step_waves<S, ROWS>())))
+__global__ __launch_bounds__(tile_lanes(TW)) __attribute__((amdgpu_waves_per_eu(step_waves<S, ROWS>())))
 void k_step(const SimDesc* __restrict__ descs,
                                                  const int2* __restrict__ sched, int p,
                                                  int row_shift, SlotArray sa) {
@@ -48,14 +65,21 @@ void k_step(const SimDesc* __restrict__ descs,
     int tx, ty;
     if (sched) {  // entry: (simulation, ty << 16 | tx)
         const int2 e = sched[blockIdx.x];
+        if (e.x < 0) return;  // a gap (uniform)
         d = descs + e.x;
         tx = e.y & 0xffff;
         ty = e.y >> 16;
+    } else if constexpr (TW == TILE_NARROW) {
+        d = descs;
+        const int tiles_y = d->tiles_y;
+        const int x = (int)(blockIdx.x & 7);
+        tx = (int)(blockIdx.x >> 3);
+        ty = (int)blockIdx.y * 8 + x;
+        if (ty >= tiles_y) return;  // beyond the last tile row (uniform)
+        ty += row_shift;
+        if (ty >= tiles_y) ty -= tiles_y;
     } else {
         d = descs;
-        // Consecutive workgroups go to the eight XCDs in turn.  Skewing the tile column by
-        // the row spreads each column, and so the longer work of the body's tiles, over
-        // all of them instead of one or two.
         const int gx = (int)gridDim.x;
         const int t = (int)blockIdx.x + (int)(blockIdx.y % gridDim.x);
         tx = t >= gx ? t - gx : t;
@@ -152,9 +176,9 @@ template <class S, bool NT, int TW>
 static void launch_step_tw(const SimDesc* dd, const int2* sched, dim3 grid, int rows, int p,
                            hipStream_t st, int row_shift, SlotArray sa) {
     switch (rows) {
-        case 1: hipLaunchKernelGGL((k_step<S, 1, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift, sa); break;
-        case 2: hipLaunchKernelGGL((k_step<S, 2, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift, sa); break;
-        default: hipLaunchKernelGGL((k_step<S, 4, NT, TW>), grid, dim3(TW), 0, st, dd, sched, p, row_shift, sa); break;
+        case 1: hipLaunchKernelGGL((k_step<S, 1, NT, TW>), grid, dim3(tile_lanes(TW)), 0, st, dd, sched, p, row_shift, sa); break;
+        case 2: hipLaunchKernelGGL((k_step<S, 2, NT, TW>), grid, dim3(tile_lanes(TW)), 0, st, dd, sched, p, row_shift, sa); break;
+        default: hipLaunchKernelGGL((k_step<S, 4, NT, TW>), grid, dim3(tile_lanes(TW)), 0, st, dd, sched, p, row_shift, sa); break;
     }
 }
 
@@ -163,6 +187,8 @@ static void launch_step_rows(const SimDesc* dd, const int2* sched, dim3 grid, in
                              int p, hipStream_t st, int row_shift, SlotArray sa) {
     if (tile_w == TILE_WIDE)
         launch_step_tw<S, NT, TILE_WIDE>(dd, sched, grid, rows, p, st, row_shift, sa);
+    else if (tile_w == TILE_NARROW)
+        launch_step_tw<S, NT, TILE_NARROW>(dd, sched, grid, rows, p, st, row_shift, sa);
     else
         launch_step_tw<S, NT, TILE_X>(dd, sched, grid, rows, p, st, row_shift, sa);
 }

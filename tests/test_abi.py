@@ -116,6 +116,7 @@ def _batch_desc(nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3):
     ("storage", 9, "storage"),
     ("rows_per_tile", 3, "rows_per_tile"),
     ("tile_width", 384, "tile_width"),
+    ("tile_width", 128, "tile_width"),
 ])
 def test_invalid_batch_options_are_rejected(lib, field, value, frag):
     descs = (vplbm.BatchDesc * 2)(_batch_desc(), _batch_desc(12, 9))

@@ -63,7 +63,10 @@ def mixed_members(storage):
                                                      ("fp16", 4, "nontemporal", 256),
                                                      ("bf16", 2, "nontemporal", 256),
                                                      ("fp32", 1, "plain", 512),
-                                                     ("fp16", 2, "nontemporal", 512)])
+                                                     ("fp16", 2, "nontemporal", 512),
+                                                     ("fp64", 1, "plain", 64),
+                                                     ("fp32", 1, "nontemporal", 64),
+                                                     ("fp16", 2, "nontemporal", 64)])
 def test_members_are_bitwise_equal_to_standalone_runs(gpu, storage, rows, store, tile):
     _flush("batch vs standalone %s rows %d %s tile %d" % (storage, rows, store, tile))
     members = mixed_members(storage)
@@ -89,11 +92,12 @@ def test_members_are_bitwise_equal_to_standalone_runs(gpu, storage, rows, store,
 
 
 @pytest.mark.parametrize("order", ["given", "largest_first", "interleaved"])
-def test_schedule_order_does_not_change_results(gpu, order):
+@pytest.mark.parametrize("tile", [256, 64])
+def test_schedule_order_does_not_change_results(gpu, order, tile):
     members = mixed_members("fp32")
-    ref = gpu.Batch(members, storage="fp32", rows=1, store="plain", order="given")
+    ref = gpu.Batch(members, storage="fp32", rows=1, store="plain", order="given", tile_width=tile)
     ref.step(20)
-    b = gpu.Batch(members, storage="fp32", rows=1, store="plain", order=order)
+    b = gpu.Batch(members, storage="fp32", rows=1, store="plain", order=order, tile_width=tile)
     b.step(20)
     for i in range(len(members)):
         assert np.array_equal(b.sims[i].get_populations(), ref.sims[i].get_populations())
@@ -101,10 +105,11 @@ def test_schedule_order_does_not_change_results(gpu, order):
     b.close()
 
 
-def test_fp64_members_match_the_oracle(gpu):
+@pytest.mark.parametrize("tile", [256, 64])
+def test_fp64_members_match_the_oracle(gpu, tile):
     from oracle import oracle as orc
     members = mixed_members("fp64")
-    batch = gpu.Batch(members, storage="fp64", rows=1, store="plain")
+    batch = gpu.Batch(members, storage="fp64", rows=1, store="plain", tile_width=tile)
     batch.step(25)
     for i in (0, 2, 4):
         spec, body = members[i]
@@ -120,17 +125,18 @@ def test_fp64_members_match_the_oracle(gpu):
     batch.close()
 
 
-def test_full_sweep_fp32_against_the_oracle(gpu):
-    """The 64-run sweep at full size (15.1 M nodes) in FP32, in the launch configuration
-    the benchmark times (one row and 256 columns per tile, nontemporal stores, the given
-    order, body states finalized in the tiles, graph replay): 10 steps from the seeded
-    near-rest state w_a (1 + 0.02 xi) written into every run, against the FP64 oracle run
-    by run.  Velocities within 1e-5 U0, penalization forces within 1e-4."""
+@pytest.mark.parametrize("tile", [64, 256])
+def test_full_sweep_fp32_against_the_oracle(gpu, tile):
+    """The 64-run sweep at full size (15.1 M nodes) in FP32, in the launch configurations
+    the benchmark times (one row per lane, 64 or 256 columns per tile, nontemporal stores,
+    the given order, body states finalized in the tiles, graph replay): 10 steps from the
+    seeded near-rest state w_a (1 + 0.02 xi) written into every run, against the FP64
+    oracle run by run.  Velocities within 1e-5 U0, penalization forces within 1e-4."""
     from oracle import oracle as orc
     sweep = W.batch_sweep(storage="fp32")
     members = [(w["spec"], w["body"]) for w in sweep]
-    _flush("full sweep fp32 vs oracle")
-    batch = gpu.Batch(members, storage="fp32", rows=1, store="nontemporal", tile_width=256,
+    _flush("full sweep fp32 vs oracle, tile %d" % tile)
+    batch = gpu.Batch(members, storage="fp32", rows=1, store="nontemporal", tile_width=tile,
                       order="given", finalize="tiles", graph_steps=2)
     f0s = []
     for k, (spec, _) in enumerate(members):
@@ -154,11 +160,11 @@ def test_full_sweep_fp32_against_the_oracle(gpu):
     batch.close()
 
 
-@pytest.mark.parametrize("storage", ["fp16", "bf16"])
-def test_full_sweep_16bit_one_step(gpu, storage):
+@pytest.mark.parametrize("storage,tile", [("fp16", 64), ("bf16", 64), ("fp16", 256)])
+def test_full_sweep_16bit_one_step(gpu, storage, tile):
     """The 64-run sweep at full size with 16-bit offset storage, in the launch
-    configuration the benchmark picks for it (one row and 256 columns per tile,
-    nontemporal stores, the given order, body states finalized by the shared launch):
+    configurations the benchmark picks for it (one row per lane, 64 or 256 columns per
+    tile, nontemporal stores, the given order, body states finalized by the shared launch):
     one step from the stored form of the seeded state, against the FP64 oracle started
     from the same stored values, run by run; the bound is the one-step storage rounding
     of the small-grid tests."""
@@ -166,7 +172,7 @@ def test_full_sweep_16bit_one_step(gpu, storage):
     sweep = W.batch_sweep(storage=storage)
     members = [(w["spec"], w["body"]) for w in sweep]
     _flush("full sweep %s one step" % storage)
-    batch = gpu.Batch(members, storage=storage, rows=1, store="nontemporal", tile_width=256,
+    batch = gpu.Batch(members, storage=storage, rows=1, store="nontemporal", tile_width=tile,
                       order="given", finalize="kernel")
     fs = []
     for k, (spec, _) in enumerate(members):
@@ -230,7 +236,7 @@ def test_batch_autotune_and_sweep(gpu):
     rows, nt, order, us = batch.autotune(trial_steps=8)
     assert rows in (1, 2, 4) and nt in (0, 1) and order in (0, 1, 2) and us > 0
     cfg = batch.sims[0].launch_config()
-    assert cfg[:2] == (rows, nt) and cfg[2] in (256, 512)
+    assert cfg[:2] == (rows, nt) and cfg[2] in (64, 256, 512)
     assert all(m.launch_config() == cfg for m in batch.sims)
     batch.step(64)
     batch.sync()

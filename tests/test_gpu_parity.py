@@ -135,13 +135,15 @@ def run_pair(gpu, spec, body, steps, seed, check_every=1, tol=1e-12, init_random
 @pytest.mark.parametrize("bcname", list(BCS))
 @pytest.mark.parametrize("bodykind", ["none", "fixed", "imposed", "free", "free_mem", "const_vel"])
 @pytest.mark.parametrize("smooth", [False, True])
-def test_tiny_grids_step_by_step_fp64(gpu, bcname, bodykind, smooth):
+@pytest.mark.parametrize("tile", [256, 64])
+def test_tiny_grids_step_by_step_fp64(gpu, bcname, bodykind, smooth, tile):
     if bodykind == "none" and smooth:
         pytest.skip("no body")
     nx, ny = 13, 11
-    _flush("tiny %s %s smooth=%s" % (bcname, bodykind, smooth))
+    _flush("tiny %s %s smooth=%s tile %d" % (bcname, bodykind, smooth, tile))
     spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04,
                    g=(2e-5, -1e-5) if bcname in ("periodic", "pipe") else (0.0, 0.0))
+    spec["tile_width"] = tile
     body = None if bodykind == "none" else body_of(bodykind, nx, ny, smooth)
     run_pair(gpu, spec, body, steps=6, seed=1234)
 
@@ -176,10 +178,12 @@ def test_tiny_grids_step_by_step_reduced(gpu, storage, bcname, bodykind):
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16", "fp32"])
 @pytest.mark.parametrize("bcname", ["channel", "periodic", "wallbox"])
-@pytest.mark.parametrize("rows,tile", [(1, 256), (2, 256), (1, 512), (2, 512), (4, 256), (4, 512)])
+@pytest.mark.parametrize("rows,tile", [(1, 256), (2, 256), (1, 512), (2, 512), (4, 256), (4, 512),
+                                       (1, 64), (2, 64), (4, 64)])
 def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows, tile):
-    """601 x 40 (three 256-column tiles or two 512-column ones, the last ragged and of odd
-    width), free body across the first 256-column border: one step at a time from the
+    """601 x 40 (three 256-column tiles, two 512-column ones or ten 64-column ones, the last
+    ragged and of odd width; 64-column tiles 4, 8 or 16 rows high, the last tile row
+    ragged), free body across the first 256-column border: one step at a time from the
     stored state, against the oracle."""
     from oracle import oracle as orc
     nx, ny = 601, 40
@@ -209,7 +213,9 @@ def test_reduced_storage_several_tiles_step_by_step(gpu, storage, bcname, rows, 
     (130, 12, 1, 256, "rows"), (130, 12, 2, 256, "rows"), (600, 9, 2, 256, "rows"),
     (600, 9, 1, 512, "rows"), (1100, 7, 2, 512, "rows"), (130, 12, 4, 256, "rows"),
     (600, 9, 4, 512, "rows"), (1100, 7, 4, 256, "rows"),
-    (130, 12, 1, 256, "planes"), (600, 9, 4, 512, "planes")])
+    (130, 12, 1, 256, "planes"), (600, 9, 4, 512, "planes"),
+    (130, 12, 1, 64, "rows"), (600, 9, 2, 64, "rows"), (131, 13, 1, 64, "planes"),
+    (66, 10, 4, 64, "rows")])
 def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows, tile, layout):
     """Grids wider than a wave: the waves holding the west or the east node of an
     interior row take the x-edge pull (the east node at 129 sits in a partly filled
@@ -230,7 +236,7 @@ def test_x_edge_waves_every_boundary_set_fp64(gpu, bcname, nx, ny, rows, tile, l
 
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
 @pytest.mark.parametrize("tile,xb,rows", [(256, 256.3, 1), (512, 511.7, 1), (256, 256.3, 4),
-                                          (512, 511.7, 4)])
+                                          (512, 511.7, 4), (64, 256.3, 1), (64, 319.7, 2)])
 def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb, rows):
     """nx = 600 spans three 256-wide tiles or two 512-wide ones, the last one ragged;
     the body straddles a tile border; one or four rows per tile."""
@@ -245,7 +251,7 @@ def test_several_tiles_and_ragged_tail_fp64(gpu, bcname, tile, xb, rows):
     run_pair(gpu, spec, b, steps=8, seed=99, check_every=2)
 
 
-@pytest.mark.parametrize("tile", [256, 512])
+@pytest.mark.parametrize("tile", [256, 512, 64])
 @pytest.mark.parametrize("fin", ["tiles", "kernel"])
 def test_body_over_more_tiles_than_a_workgroup_has_threads_fp64(gpu, tile, fin):
     """A disc of diameter 260 on a 300x300 grid: with one row per tile its participation
@@ -425,17 +431,18 @@ def test_save_and_load_resume_bitwise(gpu):
     b.close()
 
 
-def test_save_and_load_across_tile_widths(gpu):
-    """A state saved by a simulation with 256-column tiles resumes in one with 512-column
-    tiles (the body's participation box is re-expressed in the loader's tiles): the
-    continuation agrees with the saver's own to rounding."""
+@pytest.mark.parametrize("saver,loader", [(256, 512), (64, 256), (512, 64)])
+def test_save_and_load_across_tile_widths(gpu, saver, loader):
+    """A state saved by a simulation with one tile width resumes in one with another (the
+    body's participation box is re-expressed in the loader's tiles): the continuation
+    agrees with the saver's own to rounding."""
     wl = W.imposed_oscillation(storage="fp32", nx=600, ny=90, D=24.0)
     wl["body"].update(x=300.4, q0=(300.4, 45.0, 0.0), imp_y0=45.0)
-    a = gpu.Sim(dict(wl["spec"], tile_width=256), wl["body"])
+    a = gpu.Sim(dict(wl["spec"], tile_width=saver), wl["body"])
     a.step(40)
     blob = a.save()
     a.step(30)
-    b = gpu.Sim(dict(wl["spec"], tile_width=512), wl["body"])
+    b = gpu.Sim(dict(wl["spec"], tile_width=loader), wl["body"])
     b.load(blob)
     b.step(30)
     assert rel(b.get_populations(), a.get_populations()) <= 1e-6
@@ -532,7 +539,7 @@ def test_launch_configurations_agree(gpu, storage):
     populations agree to rounding (each configuration itself is deterministic)."""
     wl = W.imposed_oscillation(storage=storage, nx=600, ny=90, D=24.0)
     ref = None
-    configs = [(r, s, t) for t in (256, 512) for r in (1, 2, 4) for s in ("plain", "nontemporal")]
+    configs = [(r, s, t) for t in (256, 512, 64) for r in (1, 2, 4) for s in ("plain", "nontemporal")]
     for rows, store, tile in configs:
         g = gpu.Sim(dict(wl["spec"], rows_per_tile=rows, store_mode=store, tile_width=tile),
                     wl["body"])
@@ -553,7 +560,7 @@ def test_autotune_applies_a_configuration(gpu, tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     rows, nt, us = a.autotune(trial_steps=5, cache=cache)
     assert rows in (1, 2, 4) and nt in (0, 1) and us > 0
-    assert a.launch_config()[:2] == (rows, nt) and a.launch_config()[2] in (256, 512)
+    assert a.launch_config()[:2] == (rows, nt) and a.launch_config()[2] in (64, 256, 512)
     b = gpu.Sim(wl["spec"], wl["body"])
     rows2, nt2, us2 = b.autotune(trial_steps=5, cache=cache)  # from the cache
     assert (rows2, nt2, us2) == (rows, nt, -1.0)
@@ -628,7 +635,7 @@ def test_bgk_collision_step_by_step_fp64(gpu, bcname, bodykind):
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "periodic"])
-@pytest.mark.parametrize("rows,tile", [(1, 256), (4, 512)])
+@pytest.mark.parametrize("rows,tile", [(1, 256), (4, 512), (2, 64)])
 def test_layouts_are_bitwise_equal(gpu, storage, bcname, rows, tile):
     """The row-interleaved and the planar population layouts change addresses only:
     populations and every record field agree bitwise (a free body, a ragged last tile
@@ -655,7 +662,7 @@ def test_layouts_are_bitwise_equal(gpu, storage, bcname, rows, tile):
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-@pytest.mark.parametrize("tile", [256, 512])
+@pytest.mark.parametrize("tile", [256, 512, 64])
 def test_finalize_modes_are_bitwise_equal(gpu, storage, tile):
     """The body state made final by the next step's tiles or by a one-workgroup launch
     after each step (eager and replayed from graphs): the same fixed-order sums, so
