@@ -34,16 +34,17 @@ def _pair(gpu, spec, body, steps):
         assert np.array_equal(ra[key], rb[key]), key
 
 
-def test_static_steps_match_lbm_step_two_calls(gpu):
+@pytest.mark.parametrize("tile", [256, 64])
+def test_static_steps_match_lbm_step_two_calls(gpu, tile):
     """Two calls in a row, the second on a smaller grid with a smaller body: each is
     bitwise the plain stepping of the same simulation (the array keeps the first call's
-    contents, which the second must not read)."""
+    contents, which the second must not read); 256- or 64-column tiles."""
     wl = W.imposed_oscillation(storage="fp32", nx=600, ny=90, D=24.0)
     wl["body"].update(mode="free", free_mask=7, mass=400.0, inertia=4000.0, k=(0.01, 0.01, 0.0),
                       force_model="vp+mem")
-    _pair(gpu, wl["spec"], wl["body"], 30)
+    _pair(gpu, dict(wl["spec"], tile_width=tile), wl["body"], 30)
     small = W.imposed_oscillation(storage="fp64", nx=120, ny=48, D=12.0)
-    _pair(gpu, small["spec"], small["body"], 17)
+    _pair(gpu, dict(small["spec"], tile_width=tile), small["body"], 17)
 
 
 def test_static_and_plain_steps_interleave(gpu):
