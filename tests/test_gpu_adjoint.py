@@ -75,10 +75,13 @@ def run_gpu(gpu, spec, body, steps, every, weights, f0=None, out0=None):
 
 @pytest.mark.parametrize("bcname", list(BCS))
 @pytest.mark.parametrize("smooth", [True, False])
-def test_tiny_grids_against_the_reverse_mode_oracle(gpu, bcname, smooth):
+@pytest.mark.parametrize("tile", [256, 64])
+def test_tiny_grids_against_the_reverse_mode_oracle(gpu, bcname, smooth, tile):
+    """The forward and recomputing steps in 256- or 64-column tiles."""
     from oracle import adjoint_oracle as ado
-    _flush("adjoint tiny %s smooth=%s" % (bcname, smooth))
+    _flush("adjoint tiny %s smooth=%s tile %d" % (bcname, smooth, tile))
     spec, body = tiny(bcname, smooth)
+    spec = dict(spec, tile_width=tile)
     f0 = W.random_populations(13, 11, seed=5, amp=0.05)
     _, out0 = ado.initial_state(spec)
     out0 = out0 * (1.0 + 0.01 * np.arange(11)[None, :] / 11.0)  # a non-uniform memory
