@@ -661,6 +661,28 @@ def test_layouts_are_bitwise_equal(gpu, storage, bcname, rows, tile):
         assert np.array_equal(out[0][1][key], out[1][1][key]), key
 
 
+@pytest.mark.parametrize("tile", [64, 256])
+def test_finalize_modes_are_bitwise_equal_large_body(gpu, tile):
+    """A disc of diameter 560 on 600x600 (about 1 400 tiles of 64 columns x 4 rows, or
+    1 700 of 256 x 1): the finalize launch sums several slots per thread, several of
+    them per round of loads, the tiles one per round; the sums, hence populations and
+    records, are bitwise the same."""
+    spec = spec_of(600, 600, BCS["channel"], u_wall=UWALL, u_conv=0.04, storage="fp64")
+    spec.update(tile_width=tile, rows_per_tile=1)
+    b = W.fixed_disc(560.0, 300.3, 299.6)
+    b.update(mode="free", free_mask=7, mass=5e7, inertia=5e11, k=(0.01, 0.01, 0.0),
+             q0=(300.3, 299.6, 0.0))
+    res = []
+    for fin in ("tiles", "kernel"):
+        g = gpu.Sim(dict(spec, finalize=fin), b)
+        g.step(7)
+        res.append((g.get_populations(), g.forces()))
+        g.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    for key in ("fvp", "tvp", "pin", "fh", "th", "q", "v", "step"):
+        assert np.array_equal(res[0][1][key], res[1][1][key]), key
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("tile", [256, 512, 64])
 def test_finalize_modes_are_bitwise_equal(gpu, storage, tile):
