@@ -15,7 +15,7 @@ system moves lines of zeros faster than lines of data, so a state that still hol
 uniform inflow would overstate the rate).
 
 Prints one JSON line: MLUPS (million lattice-node updates per second) of the timed
-region, the step kernel's achieved HBM bandwidth against the 8 TB/s peak, and the FP64
+region (and the median rate of its five consecutive segments), the step kernel's achieved HBM bandwidth against the 8 TB/s peak, and the FP64
 CPU oracle timed on a bounded sample of the same workload on the host cores (all the
 cores of the GPU's share and one core).  A step is exactly one kernel launch (replayed
 from captured HIP graphs), so the kernel's average duration is the timed region's
@@ -196,18 +196,36 @@ def roofline(args, bytes_per_launch, avg_kernel_s, kernel, traffic_key):
             "algorithmic_bytes_per_launch": bytes_per_launch, "traffic_key": traffic_key}
 
 
-def timed(stream, run, steps):
+def timed(stream, run, steps, graph_steps=0, segments=5):
+    """Time exactly `steps` steps on `stream` with HIP events: returns the region's ms, its
+    wall-clock seconds and the ms per step of each of `segments` consecutive segments
+    (lengths a multiple of the captured graph's steps where the count allows; the last
+    takes the rest), whose median is reported beside the whole region's rate."""
     import torch
     print("timed %d steps" % steps, file=sys.stderr, flush=True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g = max(1, graph_steps)
+    seg = (steps // segments) // g * g or max(1, steps // segments)
+    lens = [seg] * (segments - 1)
+    lens.append(steps - sum(lens))
+    if lens[-1] <= 0:
+        lens = [steps]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(lens) + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    run(steps)
-    e1.record(stream)
+    ev[0].record(stream)
+    for k, n in enumerate(lens):
+        run(n)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1), wall
+    per = [ev[k].elapsed_time(ev[k + 1]) / n for k, n in enumerate(lens)]
+    return ev[0].elapsed_time(ev[-1]), wall, per
+
+
+def median_field(per):
+    import statistics
+    return {"median_ms_per_step_of_segments": round(statistics.median(per), 5),
+            "segment_ms_per_step": [round(x, 5) for x in per]}
 
 
 def sweep_statistics(batch, sweep, steps):
@@ -309,7 +327,7 @@ def run_batch(args):
         batch.sync()
         for m in batch.sims:
             seeded_state(m)
-        region_ms, wall = timed(stream, batch.step, steps)
+        region_ms, wall, per = timed(stream, batch.step, steps, args.graph_steps)
         batch.sync()
         layout = batch.sims[0].layout_name()
         nfin = sum(m.finalize_by_kernel() for m in batch.sims)
@@ -334,6 +352,7 @@ def run_batch(args):
                              "k_step<%s> (batched)" % args.storage, key),
         "wall_s": round(wall, 3),
     }
+    out.update(median_field(per))
     if args.accuracy_steps:
         out["accuracy_vs_fp64"] = batch_accuracy(args, vplbm, W)
     if not args.no_cpu_baseline:
@@ -382,7 +401,7 @@ def run_single(args):
         sim.step(w_post)
         sim.sync()
         seeded_state(sim)
-        region_ms, wall = timed(stream, sim.step, steps)
+        region_ms, wall, per = timed(stream, sim.step, steps, args.graph_steps)
         sim.sync()
         layout = sim.layout_name()
         fin = sim.finalize_by_kernel()
@@ -406,6 +425,7 @@ def run_single(args):
                              key),
         "wall_s": round(wall, 3),
     }
+    out.update(median_field(per))
     sim.close()
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)

@@ -290,8 +290,11 @@ int lbm_step_timed(lbm_sim* sim, int64_t n, double* kernel_ms, double* region_ms
  * and body, started from a copy of sim's current populations and outflow memory (call it
  * once the flow has developed: the uniform start state is exactly zero in offsets and
  * moves faster than a developed flow): two replays of a captured graph of trial_steps
- * steps (rounded down to even, at least 2), the faster counting.  It then applies the
- * fastest to sim (whose state is not touched).  cache_path (may be NULL) names a
+ * steps (rounded down to even, at least 2), the faster counting.  It then applies to
+ * sim (whose state is not touched) the fastest, or rather, of the candidates within 1 %
+ * of the fastest, the one with the narrowest tiles (then the fewest rows per lane, plain
+ * stores, the state finalized in the tiles): equal within the timing's spread, it reads
+ * the fewest bytes.  cache_path (may be NULL) names a
  * JSON-lines file: a configuration found there for this device, storage and grid is
  * applied without timing, and a newly timed one is appended.  Outputs (each may be
  * NULL): the chosen rows, nt flag, and the measured time per step in microseconds (-1
@@ -381,8 +384,10 @@ int lbm_batch_configure(lbm_batch* batch, int rows, int store_mode, int order);
 /* Chooses rows, store mode, columns per tile, order and (with bodies) how the body
  * states are finalized by timing each candidate on a scratch copy of the batch started
  * from the members' current states (as lbm_autotune: the faster of two replays of a
- * captured graph of trial_steps steps), then applies them (members' states are not
- * touched; lbm_launch_config and lbm_finalize_by_kernel on a member report the choice).
+ * captured graph of trial_steps steps; rows, store mode and columns per tile by the
+ * near-tie rule of lbm_autotune, then the order and the finalization by the faster),
+ * then applies them (members' states are not touched; lbm_launch_config and
+ * lbm_finalize_by_kernel on a member report the choice).
  * Outputs may be NULL; us_out is the time per batch step in microseconds. */
 int lbm_batch_autotune(lbm_batch* batch, int trial_steps, int* rows_out, int* nt_out,
                        int* order_out, double* us_out);

@@ -834,6 +834,23 @@ static int apply_launch_config(lbm_sim* s, int rows, bool nt, int tile_w) {
     return LBM_OK;
 }
 
+// The autotuners' choice among timed candidates: of those within 1 % of the fastest,
+// the one of lowest rank (rank orders narrower tiles first, then fewer rows per lane,
+// plain stores before nontemporal ones, the body state finalized in the tiles before
+// the extra launch).  Candidates that close are equal within the timing's spread, and
+// narrower tiles read fewer bytes (the cache lines that x-shifted pulls straddle are
+// shared by tiles that run one after the other on one XCD); the rule also keeps the
+// choice from changing with the spread from one run to the next.
+constexpr double TUNE_TIE = 0.01;
+static int pick_near_fastest(const double* us, const int* rank, int n) {
+    double fastest = us[0];
+    for (int k = 1; k < n; ++k) fastest = std::min(fastest, us[k]);
+    int pick = -1;
+    for (int k = 0; k < n; ++k)
+        if (us[k] <= fastest * (1.0 + TUNE_TIE) && (pick < 0 || rank[k] < rank[pick])) pick = k;
+    return pick;
+}
+
 static std::string tune_key(const lbm_sim* s) {
     hipDeviceProp_t prop;
     int dev = 0;
@@ -904,6 +921,7 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
         // with a body, both ways of finalizing its state are timed
         const int cand_fin[2] = {LBM_FINALIZE_TILES, LBM_FINALIZE_KERNEL};
         const int ncand = s->has_body ? 36 : 18;
+        double cand_us[36];
         for (int cj = 0; cj < ncand; ++cj) {
             const int ci = cj % 18;
             lbm_opts o = s->opts;
@@ -945,15 +963,18 @@ int lbm_autotune(lbm_sim* s, int trial_steps, const char* cache_path, int* rows_
             if (e1) (void)hipEventDestroy(e1);
             lbm_destroy(t);
             if (!ok) return fail(s, LBM_ERR_HIP, "autotune: timing run failed");
-            const double us = 1e3 * best_ms / gs;
-            if (best < 0.0 || us < best) {
-                best = us;
-                rows = cand_rows[(ci / 2) % 3];
-                nt = ci & 1;
-                tile_w = cand_w[ci / 6];
-                fin = s->has_body ? cand_fin[cj / 18] : LBM_FINALIZE_AUTO;
-            }
+            cand_us[cj] = 1e3 * best_ms / gs;
         }
+        // candidate cj: tile width cj % 18 / 6, rows (cj % 18 / 2) % 3, store cj % 2,
+        // finalization cj / 18
+        int rank[36];
+        for (int k = 0; k < ncand; ++k) rank[k] = 2 * (k % 18) + k / 18;
+        const int cj = pick_near_fastest(cand_us, rank, ncand), ci = cj % 18;
+        best = cand_us[cj];
+        rows = cand_rows[(ci / 2) % 3];
+        nt = ci & 1;
+        tile_w = cand_w[ci / 6];
+        fin = s->has_body ? cand_fin[cj / 18] : LBM_FINALIZE_AUTO;
         if (cache_path) {
             FILE* f = std::fopen(cache_path, "a");
             if (f) {
@@ -1560,13 +1581,13 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* rows_out, int* nt_out
             if (rc) return rc;
             cand_us[ci] = pass == 0 ? us : std::min(cand_us[ci], us);
         }
-    for (int ci = 0; ci < 18; ++ci)
-        if (best < 0 || cand_us[ci] < best) {
-            best = cand_us[ci];
-            best_rows = cand_rows[(ci / 2) % 3];
-            best_nt = ci & 1;
-            best_w = cand_w[ci / 6];
-        }
+    int rank[18];
+    for (int k = 0; k < 18; ++k) rank[k] = k;  // width ci / 6, rows (ci / 2) % 3, store ci % 2
+    const int ci = pick_near_fastest(cand_us, rank, 18);
+    best = cand_us[ci];
+    best_rows = cand_rows[(ci / 2) % 3];
+    best_nt = ci & 1;
+    best_w = cand_w[ci / 6];
     for (int order : {LBM_ORDER_GIVEN, LBM_ORDER_INTERLEAVED}) {
         int rc = batch_time(b, best_rows, best_nt, order, best_w, LBM_FINALIZE_AUTO, trial_steps, us);
         if (rc) return rc;
