@@ -160,6 +160,38 @@ def test_full_sweep_fp32_against_the_oracle(gpu, tile):
     batch.close()
 
 
+def test_full_sweep_fp64_against_the_oracle(gpu):
+    """The 64-run sweep at full size in FP64 (the reference against which the reduced
+    storages' drag and lift are measured), in the launch configuration the benchmark picks
+    for it (one row per lane, 64 columns per tile, nontemporal stores, the given order,
+    graph replay): 10 steps from the seeded state against the FP64 oracle, run by run, to
+    1e-12 in populations and penalization force."""
+    from oracle import oracle as orc
+    sweep = W.batch_sweep(storage="fp64")
+    members = [(w["spec"], w["body"]) for w in sweep]
+    _flush("full sweep fp64 vs oracle")
+    batch = gpu.Batch(members, storage="fp64", rows=1, store="nontemporal", tile_width=64,
+                      order="given", finalize="tiles", graph_steps=2)
+    f0s = []
+    for k, (spec, _) in enumerate(members):
+        f0 = W.random_populations(spec["nx"], spec["ny"], seed=2024 + k, amp=0.02)
+        batch.sims[k].set_populations(f0)
+        f0s.append(f0)
+    batch.step(10)
+    batch.sync()
+    worst_f, worst_r = 0.0, 0.0
+    for k, (spec, body) in enumerate(members):
+        o = orc.OracleSim(spec, body)
+        o.set_populations(f0s[k])
+        ro = o.step(10)
+        ef = rel(batch.sims[k].get_populations(), o.get_populations())
+        er = rel(batch.sims[k].forces()["fvp"], ro["fvp"])
+        worst_f, worst_r = max(worst_f, ef), max(worst_r, er)
+        assert ef <= 1e-12 and er <= 1e-12, (k, ef, er)
+    _flush("full sweep fp64: population err %.2e, force err %.2e" % (worst_f, worst_r))
+    batch.close()
+
+
 @pytest.mark.parametrize("storage,tile", [("fp16", 64), ("bf16", 64), ("fp16", 256)])
 def test_full_sweep_16bit_one_step(gpu, storage, tile):
     """The 64-run sweep at full size with 16-bit offset storage, in the launch
