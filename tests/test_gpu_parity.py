@@ -148,6 +148,39 @@ def test_tiny_grids_step_by_step_fp64(gpu, bcname, bodykind, smooth, tile):
     run_pair(gpu, spec, body, steps=6, seed=1234)
 
 
+@pytest.mark.parametrize("bcname", list(BCS))
+@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 17), (17, 3), (65, 3), (4, 4), (66, 5)])
+@pytest.mark.parametrize("tile,rows", [(256, 1), (64, 1), (64, 4), (512, 2)])
+def test_smallest_grids_step_by_step_fp64(gpu, bcname, nx, ny, tile, rows):
+    """Grids of the smallest allowed sizes (three nodes a side), with rows or columns of
+    three and a partly filled wave: every node is an edge node, or every wave holds both
+    x edges; a free disc of radius 1.1 near the centre.  4 steps against the oracle."""
+    _flush("smallest %s %dx%d tile %d rows %d" % (bcname, nx, ny, tile, rows))
+    spec = spec_of(nx, ny, BCS[bcname], u_wall=UWALL, u_conv=0.04,
+                   g=(2e-5, -1e-5) if bcname in ("periodic", "pipe") else (0.0, 0.0))
+    spec.update(tile_width=tile, rows_per_tile=rows)
+    b = W.fixed_disc(2.2, nx / 2.0 - 0.3, ny / 2.0 + 0.2)
+    b.update(mode="free", free_mask=7, mass=50.0, inertia=30.0, k=(0.01, 0.01, 0.0),
+             q0=(b["x"], b["y"], 0.0), force_model="vp+mem")
+    run_pair(gpu, spec, b, steps=4, seed=17)
+
+
+def test_zero_steps_and_empty_records(gpu):
+    """Stepping zero steps does nothing (no record, the populations unchanged); forces
+    with nothing pending returns no record."""
+    wl = W.imposed_oscillation(storage="fp64", nx=40, ny=20, D=6.0)
+    g = gpu.Sim(wl["spec"], wl["body"])
+    f0 = g.get_populations()
+    g.step(0)
+    assert len(g.forces()) == 0 and g.step_index() == 0
+    assert np.array_equal(g.get_populations(), f0)
+    g.step(3)
+    assert len(g.forces()) == 3 and len(g.forces()) == 0
+    g.step(0)
+    assert g.step_index() == 3 and len(g.forces()) == 0
+    g.close()
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("bcname", ["channel", "wallbox", "mixed", "pipe"])
 @pytest.mark.parametrize("bodykind", ["fixed", "free"])
