@@ -264,11 +264,15 @@ int lbm_sync(lbm_sim* sim);
 int lbm_forces(lbm_sim* sim, lbm_force_rec* out, int64_t cap, int64_t* n_out);
 
 /* Synchronises, then writes density and penalized velocity (Eq. (22)) of the current
- * state with the body at its current pose into host arrays of nx*ny doubles each. */
+ * state with the body at its current pose into host arrays of nx*ny doubles each.  The
+ * first call of lbm_fields, lbm_set_populations or lbm_get_populations on a simulation
+ * allocates its FP64 exchange buffer on the device (9 nx ny doubles, kept until
+ * lbm_destroy); LBM_ERR_ALLOC if that fails. */
 int lbm_fields(lbm_sim* sim, double* rho, double* ux, double* uy);
 
 /* Debug access to the post-collision populations f (not offsets), host FP64
- * [9][ny][nx]; set is rounded to the storage precision. */
+ * [9][ny][nx]; set is rounded to the storage precision.  See lbm_fields for the exchange
+ * buffer. */
 int lbm_set_populations(lbm_sim* sim, const double* f);
 int lbm_get_populations(lbm_sim* sim, double* f);
 

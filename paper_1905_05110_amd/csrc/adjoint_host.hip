@@ -660,6 +660,8 @@ int lbm_adjoint_gradient(lbm_adjoint* A, double* dJ_dchi, double* dJ_dpos, doubl
     if (!A) return LBM_ERR_ARG;
     if (!A->bwd_done) return afail(A, LBM_ERR_STATE, "lbm_adjoint_backward must run first");
     lbm_sim* s = A->sim;
+    if (dJ_dchi && ensure_staging(s) != hipSuccess)
+        return afail(A, LBM_ERR_ALLOC, "hipMalloc of the FP64 exchange buffer failed");
     double r[5];
     dispatch(A->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;

@@ -328,7 +328,6 @@ int lbm_create(int nx, int ny, lbm_rates rates, double eta, const lbm_opts* opts
     CREATE_TRY(hipMalloc((void**)&s->partials, 2 * (size_t)ntiles * NRED * sizeof(double)));
     CREATE_TRY(hipMalloc((void**)&s->hist, (size_t)s->hist_cap * sizeof(Record)));
     CREATE_TRY(hipMalloc((void**)&s->flag, 64));
-    CREATE_TRY(hipMalloc((void**)&s->staging, (size_t)NQ * nx * ny * sizeof(double)));
     CREATE_TRY(hipMalloc((void**)&s->desc_d, sizeof(SimDesc)));
 
     SimDesc& d = s->desc;
@@ -745,6 +744,8 @@ int lbm_forces(lbm_sim* s, lbm_force_rec* out, int64_t cap, int64_t* n_out) {
 int lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy) {
     if (!s || !rho || !ux || !uy) return fail(s, LBM_ERR_ARG, "NULL argument");
     const int p = (int)(s->host_step & 1);
+    if (ensure_staging(s) != hipSuccess)
+        return fail(s, LBM_ERR_ALLOC, "hipMalloc of the FP64 exchange buffer failed");
     int frc = flush_state(s);
     if (frc) return frc;
     dispatch(s->storage, [&](auto* tag) {
@@ -763,6 +764,8 @@ int lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy) {
 
 int lbm_set_populations(lbm_sim* s, const double* f) {
     if (!s || !f) return fail(s, LBM_ERR_ARG, "NULL argument");
+    if (ensure_staging(s) != hipSuccess)
+        return fail(s, LBM_ERR_ALLOC, "hipMalloc of the FP64 exchange buffer failed");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const size_t n = (size_t)NQ * s->nx * s->ny;
     HIP_TRY(s, hipMemcpy(s->staging, f, n * 8, hipMemcpyHostToDevice));
@@ -779,6 +782,8 @@ int lbm_set_populations(lbm_sim* s, const double* f) {
 
 int lbm_get_populations(lbm_sim* s, double* f) {
     if (!s || !f) return fail(s, LBM_ERR_ARG, "NULL argument");
+    if (ensure_staging(s) != hipSuccess)
+        return fail(s, LBM_ERR_ALLOC, "hipMalloc of the FP64 exchange buffer failed");
     const int p = (int)(s->host_step & 1);
     dispatch(s->storage, [&](auto* tag) {
         using S = std::remove_pointer_t<decltype(tag)>;

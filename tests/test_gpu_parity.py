@@ -165,6 +165,34 @@ def test_smallest_grids_step_by_step_fp64(gpu, bcname, nx, ny, tile, rows):
     run_pair(gpu, spec, b, steps=4, seed=17)
 
 
+@pytest.mark.parametrize("tile", [256, 64])
+def test_largest_rows_layout_grid_is_periodic_after_a_step(gpu, tile):
+    """The largest FP32 grid the row-interleaved layout takes (11264 x 10560: a population
+    buffer of 4.28 GB, 99.7 % of the 4 GiB that 32-bit byte offsets address), periodic on
+    every side and started from a seeded 64 x 64 pattern repeated over it: after one step
+    every 64 x 64 block is bitwise the step of that pattern on its own periodic 64 x 64
+    grid, so no node far into the buffer reads or writes a wrong address."""
+    nx, ny, n = 11264, 10560, 64
+    spec = spec_of(nx, ny, BCS["periodic"], storage="fp32", g=(2e-5, -1e-5))
+    spec.update(tile_width=tile, rows_per_tile=1, layout="rows")
+    assert gpu.load_library().lbm_pop_bytes(nx, ny, gpu.STORAGE["fp32"]) < (1 << 32)
+    pat = W.random_populations(n, n, seed=91, amp=0.05)
+    small = gpu.Sim(dict(spec, nx=n, ny=n), None)
+    small.set_populations(pat)
+    small.step(1)
+    ref = small.get_populations()
+    small.close()
+    _flush("largest rows-layout grid %dx%d tile %d" % (nx, ny, tile))
+    big = gpu.Sim(spec, None)
+    assert big.layout_name() == "rows"
+    big.set_populations(np.tile(pat, (1, ny // n, nx // n)))
+    big.step(1)
+    f = big.get_populations()
+    big.close()
+    blocks = f.reshape(9, ny // n, n, nx // n, n)
+    assert np.array_equal(blocks, np.broadcast_to(ref[:, None, :, None, :], blocks.shape))
+
+
 def test_zero_steps_and_empty_records(gpu):
     """Stepping zero steps does nothing (no record, the populations unchanged); forces
     with nothing pending returns no record."""
