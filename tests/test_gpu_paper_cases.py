@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 from paper_1905_05110_amd import workloads as W
+from golden import value as printed
 
 pytestmark = pytest.mark.gpu
 
@@ -69,10 +70,10 @@ def test_paper_imposed_oscillation_mean_drag(gpu):
     cd_mem = r["fmem"][:, 0].mean() / s
     cd_h = r["fh"][:, 0].mean() / s
     _flush("moving, %d periods: mean CD %.4f (momentum exchange), %.4f (penalization); "
-           "paper 1.653" % (k, cd_mem, cd_h))
+           "paper %.3f" % (k, cd_mem, cd_h, printed("mean_cd_imposed_oscillation")))
     y = r["q"][:, 1]
     assert abs(y.max() - wl["fixed"]["y"]) < 1e-9 and abs(y.min() - (wl["fixed"]["y"] - 2 * wl["body"]["imp_amp"])) < 1e-3
-    assert abs(cd_mem / 1.653 - 1.0) <= 0.02
+    assert abs(cd_mem / printed("mean_cd_imposed_oscillation") - 1.0) <= 0.02
     assert abs(cd_h / cd_mem - 1.0) <= 0.01
 
 
@@ -142,9 +143,10 @@ def test_paper_viv_effective_stiffness(gpu):
         keff = w["k_star"] - w["m_star"] * om ** 2
         res[w["k_star"]] = (amp, keff)
         _flush("k* %g: amplitude %.3f D, omega* %.4f, k*_eff %.3f" % (w["k_star"], amp, om, keff))
-    assert abs(res[9.0][1] - 0.058) <= 0.15
-    assert abs(res[19.0][1] - 3.20) <= 1.5
-    assert abs(res[28.0][1] - 16.37) <= 0.3  # the calibration point of m* (not a check)
+    assert abs(res[9.0][1] - printed("keff_vortex_induced_k9")) <= 0.15
+    assert abs(res[19.0][1] - printed("keff_vortex_induced_k19")) <= 1.5
+    # the calibration point of m* (not a check)
+    assert abs(res[28.0][1] - printed("keff_vortex_induced_k28")) <= 0.3
     assert max(res[9.0][0], res[19.0][0]) > 0.5  # lock-in: more than half a diameter
     assert res[28.0][0] < 0.1  # far from lock-in the displacement stays small
 
@@ -164,9 +166,10 @@ def test_paper_offcentre_settling(gpu):
     D, nu = w["D"], w["nu"]
     y = r["q"][:, 1] - yc
     re = r["v"][-5000:, 0].mean() * D / nu
-    _flush("final Re %.3f (paper 8.33); max overshoot %.3f D; final offset %.4f D; first "
-           "rotation %.2e" % (re, y.max() / D, y[-1] / D, r["v"][2000, 2]))
-    assert abs(re / 8.33 - 1.0) <= 0.03
+    re_paper = printed("reynolds_offcentre_settling")
+    _flush("final Re %.3f (paper %.2f); max overshoot %.3f D; final offset %.4f D; first "
+           "rotation %.2e" % (re, re_paper, y.max() / D, y[-1] / D, r["v"][2000, 2]))
+    assert abs(re / re_paper - 1.0) <= 0.03
     assert y[0] < -D  # released near the wall ...
     assert r["v"][2000, 1] > 0.0 and r["v"][2000, 2] > 0.0  # ... moving off it, turning positively
     assert y.max() > 0.05 * D  # crosses the centre line once (brief oscillation)
