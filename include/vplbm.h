@@ -76,7 +76,8 @@ enum { LBM_REF_AUTO = 0, LBM_REF_INITIAL = 1, LBM_REF_REST = 2 };
 enum { LBM_STORE_AUTO = 0, LBM_STORE_PLAIN = 1, LBM_STORE_NONTEMPORAL = 2 };
 
 /* Arrangement of the nine population arrays of a buffer (each row of a direction holds
- * pitch = nx rounded up to 64 elements):
+ * pitch = nx rounded up to an odd multiple of 64 elements; the padding is never read or
+ * written):
  *   ROWS    row-interleaved: row j of direction a at element (9 j + a) pitch, so that the
  *           three source rows and the destination row of a node lie close together;
  *   PLANES  one plane per direction, [9][ny][pitch] plus a small pad between planes;

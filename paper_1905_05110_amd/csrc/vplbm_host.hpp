@@ -19,24 +19,32 @@ inline size_t elem_size(int storage) {
     }
 }
 
+// Row stride of a single-field array (elements): nx rounded up to 64.
 inline int row_pitch(int nx) { return (nx + 63) / 64 * 64; }
+
+// Row stride of the population arrays (elements): nx rounded up to an odd multiple of
+// 64.  Tiles of consecutive rows run at once on different XCDs; with a row stride of
+// 2^k x 64 elements (k >= 2) their accesses fall on the same few memory channels, and
+// 64-column tiles of 512-, 768- or 1024-column grids ran 5-10 % slower than those of
+// 576 or 704 columns.  The padding columns are never read or written.
+inline int pop_row_pitch(int nx) { return ((nx + 63) / 64 | 1) * 64; }
 
 inline long long plane_stride(int nx, int ny) {
     // pad planes by 5 x 64 elements so the nine streams do not start on the same
     // large power-of-two boundary
-    return (long long)row_pitch(nx) * ny + 320;
+    return (long long)pop_row_pitch(nx) * ny + 320;
 }
 
 // Strides of the population arrays of one buffer (elements): between the rows of one
 // direction (SimDesc::pitch) and between directions (SimDesc::ps).  ROWS puts row j of
-// direction a at (9 j + a) row_pitch: the rows a node's pull reads and the row it writes
+// direction a at (9 j + a) pop_row_pitch: the rows a node's pull reads and the row it writes
 // then lie within a few row lengths of each other, which the memory system serves
 // faster than nine separate planes.  Kernels address populations with 32-bit byte
 // offsets from a direction's base, so ROWS needs the whole buffer, PLANES one plane,
 // below 4 GiB; returns false (with a message) when the request does not fit.
 inline bool pop_geometry(int nx, int ny, int storage, int request, int& pitch, long long& ps,
                          int& layout, std::string& msg) {
-    const long long rp = row_pitch(nx);
+    const long long rp = pop_row_pitch(nx);
     const long long e = (long long)elem_size(storage);
     const long long lim = 1LL << 32;
     const bool rows_fit = (long long)NQ * rp * ny * e < lim;

@@ -167,12 +167,13 @@ def test_smallest_grids_step_by_step_fp64(gpu, bcname, nx, ny, tile, rows):
 
 @pytest.mark.parametrize("tile", [256, 64])
 def test_largest_rows_layout_grid_is_periodic_after_a_step(gpu, tile):
-    """The largest FP32 grid the row-interleaved layout takes (11264 x 10560: a population
-    buffer of 4.28 GB, 99.7 % of the 4 GiB that 32-bit byte offsets address), periodic on
-    every side and started from a seeded 64 x 64 pattern repeated over it: after one step
-    every 64 x 64 block is bitwise the step of that pattern on its own periodic 64 x 64
-    grid, so no node far into the buffer reads or writes a wrong address."""
-    nx, ny, n = 11264, 10560, 64
+    """The largest FP32 grid the row-interleaved layout takes (11200 x 10624, rows of an
+    odd multiple of 64 elements: a population buffer of 4.28 GB, 99.7 % of the 4 GiB that
+    32-bit byte offsets address), periodic on every side and started from a seeded 64 x 64
+    pattern repeated over it: after one step every 64 x 64 block is bitwise the step of
+    that pattern on its own periodic 64 x 64 grid, so no node far into the buffer reads or
+    writes a wrong address."""
+    nx, ny, n = 11200, 10624, 64
     spec = spec_of(nx, ny, BCS["periodic"], storage="fp32", g=(2e-5, -1e-5))
     spec.update(tile_width=tile, rows_per_tile=1, layout="rows")
     assert gpu.load_library().lbm_pop_bytes(nx, ny, gpu.STORAGE["fp32"]) < (1 << 32)
