@@ -93,6 +93,17 @@ def test_null_handles_are_rejected(lib):
     assert lib.lbm_pop_bytes(10, 5, 1) > 9 * 10 * 5 * 4
 
 
+@pytest.mark.parametrize("nx,rp", [(3, 64), (64, 64), (65, 192), (128, 192), (500, 576),
+                                   (512, 576), (576, 576), (640, 704), (1024, 1088),
+                                   (8192, 8256)])
+def test_population_rows_are_padded_to_an_odd_multiple_of_64(lib, nx, rp):
+    # lbm_pop_bytes = 9 (rp ny + 320) elements, rp the row pitch: nx rounded up to an odd
+    # multiple of 64 elements, in every storage
+    ny = 7
+    for storage, e in ((0, 8), (1, 4), (2, 2), (3, 2)):
+        assert lib.lbm_pop_bytes(nx, ny, storage) == 9 * (rp * ny + 320) * e
+
+
 def test_create_without_device_reports_hip_error(lib):
     import torch
     if torch.cuda.is_available():
