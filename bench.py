@@ -196,11 +196,34 @@ def roofline(args, bytes_per_launch, avg_kernel_s, kernel, traffic_key):
             "algorithmic_bytes_per_launch": bytes_per_launch, "traffic_key": traffic_key}
 
 
+def keep_busy(stream, ms=60.0):
+    """Read passes over a 512 MiB device buffer on `stream`, about `ms` of GPU time, that
+    touch nothing of the simulation (returns what must live until the stream has passed
+    them)."""
+    import torch
+    with torch.cuda.stream(stream):
+        buf = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        acc = torch.zeros((), dtype=torch.float32, device="cuda")
+        for _ in range(int(ms * 1e-3 / 80e-6)):  # one pass reads 512 MiB in about 80 us
+            acc += buf.sum()
+    return buf, acc
+
+
 def timed(stream, run, steps, graph_steps=0, segments=5):
     """Time exactly `steps` steps on `stream` with HIP events: returns the region's ms, its
     wall-clock seconds and the ms per step of each of `segments` consecutive segments
     (lengths a multiple of the captured graph's steps where the count allows; the last
-    takes the rest), whose median is reported beside the whole region's rate."""
+    takes the rest), whose median is reported beside the whole region's rate.
+
+    The region's opening event is queued behind some 60 ms of unrelated device work
+    (keep_busy), and the steps behind it, while that work runs: the timed steps then run
+    back to back from the event on, as they do in a long run, instead of the region
+    opening on an idle stream and waiting for the host to submit the first step (20-50
+    us), and they start on a GPU that has been working rather than one that sat idle
+    while the host wrote the seeded state (after seconds idle the step time rises by up
+    to 8 % for some tens of steps while the power state settles).  A region of 20 steps
+    would otherwise count both against the step's rate.  The wall-clock time runs from
+    the moment the opening event has passed to the end."""
     import torch
     print("timed %d steps" % steps, file=sys.stderr, flush=True)
     g = max(1, graph_steps)
@@ -211,13 +234,17 @@ def timed(stream, run, steps, graph_steps=0, segments=5):
         lens = [steps]
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(lens) + 1)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    busy = keep_busy(stream)
     ev[0].record(stream)
     for k, n in enumerate(lens):
         run(n)
         ev[k + 1].record(stream)
+    while not ev[0].query():
+        pass
+    t0 = time.perf_counter()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    del busy
     per = [ev[k].elapsed_time(ev[k + 1]) / n for k, n in enumerate(lens)]
     return ev[0].elapsed_time(ev[-1]), wall, per
 
