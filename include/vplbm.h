@@ -81,11 +81,14 @@ enum { LBM_STORE_AUTO = 0, LBM_STORE_PLAIN = 1, LBM_STORE_NONTEMPORAL = 2 };
  *   ROWS    row-interleaved: row j of direction a at element (9 j + a) pitch, so that the
  *           three source rows and the destination row of a node lie close together;
  *   PLANES  one plane per direction, [9][ny][pitch] plus a small pad between planes;
- *   AUTO    ROWS when the whole buffer is below 4 GiB (population addresses are 32-bit
- *           byte offsets from a direction's base), else PLANES.
- * PLANES needs each plane below 4 GiB (about 1.07 G nodes in FP32, 537 M in FP64);
- * lbm_create refuses larger grids with LBM_ERR_ARG.  Both take lbm_pop_bytes() bytes;
- * results are bitwise the same in either. */
+ *   AUTO    ROWS when it fits, else PLANES.
+ * Buffers may be of any size: the step addresses each tile's populations with 32-bit
+ * offsets from bases at the tile's own rows, the other paths with 64-bit offsets.  The
+ * 18 rows a tile reaches must span less than 4 GiB: ROWS takes up to 3.3 M columns in
+ * FP64 (6.6 M in FP32, 13 M in 16-bit storage), PLANES nine times as many; lbm_create
+ * refuses wider grids with LBM_ERR_ARG (and the adjoint, whose reverse step uses 32-bit
+ * offsets from a direction's base, refuses grids whose direction arrays reach 4 GiB).
+ * Both take lbm_pop_bytes() bytes; results are bitwise the same in either. */
 enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_ROWS = 1, LBM_LAYOUT_PLANES = 2 };
 
 /* Where the body state of a step is made final.  The tiles that meet the body write

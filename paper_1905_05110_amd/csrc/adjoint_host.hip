@@ -364,6 +364,10 @@ int lbm_adjoint_create(int nx, int ny, lbm_rates rates, double eta, const lbm_op
     int rc = lbm_create(nx, ny, rates, eta, &o, &A->sim);
     if (rc) return A->err = lbm_last_error(nullptr), bail(rc);
     lbm_sim* s = A->sim;
+    // the reverse step addresses a direction's populations with 32-bit byte offsets
+    if ((long long)s->desc.pitch * ny * (long long)vplbm::elem_size(o.storage) >= (1LL << 32))
+        return A->err = "grid too large for the adjoint (a direction's populations reach 4 GiB)",
+               bail(LBM_ERR_ARG);
     rc = lbm_set_body(s, body);
     if (rc) return A->err = s->err, bail(rc);
     A->storage = o.storage;

@@ -107,8 +107,9 @@ __device__ __forceinline__ void adjoint_node(const SimDesc& d, const AdjDesc& a,
             const char* P[NQ];
 #pragma unroll
             for (int b = 0; b < NQ; ++b) P[b] = plane<S>(d, fin, b);
-            pull_interior<S>(P, node_off<S>(d, i, j), (unsigned)d.pitch * (unsigned)sizeof(S), 1.0f,
-                             g);
+            // 32-bit offsets: the adjoint refuses grids whose direction arrays reach 4 GiB
+            pull_interior<S>(P, (unsigned)node_off<S>(d, i, j), (unsigned)d.pitch * (unsigned)sizeof(S),
+                             1.0f, g);
         } else {
             pull_edge<S>(d, fin, outk, i, j, g, false);
         }

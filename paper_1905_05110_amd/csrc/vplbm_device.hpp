@@ -272,9 +272,12 @@ __device__ __forceinline__ void raise_flag(int* flag, int bits) {
                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Byte offset of node (i, j) from a direction's base, 64-bit: the paths off the tile's
+// fast path (edge pulls, import, export, the exchange pass) address any buffer size this
+// way, at the cost of a per-lane 64-bit address.
 template <class S>
-__device__ __forceinline__ unsigned node_off(const SimDesc& d, int i, int j) {
-    return ((unsigned)j * (unsigned)d.pitch + (unsigned)i) * (unsigned)sizeof(S);
+__device__ __forceinline__ long long node_off(const SimDesc& d, int i, int j) {
+    return ((long long)j * d.pitch + i) * (long long)sizeof(S);
 }
 
 template <class S>
@@ -288,12 +291,18 @@ __device__ __forceinline__ const char* plane(const SimDesc& d, const void* buf, 
 // scalar registers; read from the descriptor where they are used, after a load or an
 // atomic the compiler has to order them behind, each came back as a vector load with
 // a full memory round trip of its own.
+// The fast path addresses populations with 32-bit lane offsets from bases that the tile
+// moves to its own rows: fin and fout point at row jb, the row above the tile's first
+// (-1 for the first tile row: an address below the buffer that is never accessed), and a
+// node (i, j) of the tile or of the rows next to it lies at byte offset
+// ((j - jb) pitch + i) sizeof(S) from them, whatever the size of the buffer.
 template <class T>
 struct TileScalars {
-    const char* fin;   // populations read by the step
-    char* fout;        // populations written
+    const char* fin;   // populations read by the step, from row jb on
+    char* fout;        // populations written, from row jb on
     long long psb;     // plane stride in bytes
     unsigned rowb;     // row pitch in bytes
+    int jb;            // the row fin and fout point at
     int pitch, nx, ny;
     float scale, inv_scale;
     int* flag;
@@ -301,12 +310,16 @@ struct TileScalars {
 };
 
 template <class S>
-__device__ __forceinline__ TileScalars<typename Codec<S>::T> tile_scalars(const SimDesc& d, int p) {
+__device__ __forceinline__ TileScalars<typename Codec<S>::T> tile_scalars(const SimDesc& d, int p,
+                                                                         int jb) {
     using T = typename Codec<S>::T;
     const Consts<T>& c = consts_of<T>(d);
     TileScalars<T> t;
-    t.fin = reinterpret_cast<const char*>(d.pop[p]);
-    t.fout = reinterpret_cast<char*>(d.pop[p ^ 1]);
+    // integer arithmetic: the base of the first tile row lies below the buffer
+    const long long rel = (long long)jb * d.pitch * (long long)sizeof(S);
+    t.fin = reinterpret_cast<const char*>(reinterpret_cast<uintptr_t>(d.pop[p]) + rel);
+    t.fout = reinterpret_cast<char*>(reinterpret_cast<uintptr_t>(d.pop[p ^ 1]) + rel);
+    t.jb = jb;
     t.psb = d.ps * (long long)sizeof(S);
     t.pitch = d.pitch;
     t.rowb = (unsigned)d.pitch * (unsigned)sizeof(S);
@@ -353,7 +366,7 @@ __device__ bool pull_rules(const SimDesc& d, const void* fin, int a, int i, int 
         } else if (kind == BC_OUTFLOW) {
             return false;
         } else {  // WALL or VELOCITY: half-way bounce-back of the population leaving (i, j)
-            out = Codec<S>::load(plane<S>(d, fin, dir_opp(a)), node_off<S>(d, i, j), d.inv_scale) +
+            out = Codec<S>::load(plane<S>(d, fin, dir_opp(a)) + node_off<S>(d, i, j), 0u, d.inv_scale) +
                   c.bb[side][a];
             return true;
         }
@@ -367,12 +380,12 @@ __device__ bool pull_rules(const SimDesc& d, const void* fin, int a, int i, int 
             dir = dir_flip_y(dir);
             sj = j;
         } else {
-            out = Codec<S>::load(plane<S>(d, fin, dir_opp(a)), node_off<S>(d, i, j), d.inv_scale) +
+            out = Codec<S>::load(plane<S>(d, fin, dir_opp(a)) + node_off<S>(d, i, j), 0u, d.inv_scale) +
                   c.bb[side][a];
             return true;
         }
     }
-    out = Codec<S>::load(plane<S>(d, fin, dir), node_off<S>(d, si, sj), d.inv_scale);
+    out = Codec<S>::load(plane<S>(d, fin, dir) + node_off<S>(d, si, sj), 0u, d.inv_scale);
     if (dir != a) out += c.dref[a][dir];  // specular reflection between directions
     return true;
 }
@@ -402,14 +415,14 @@ __device__ __forceinline__ double uniform_value(double x) {
 // the next step (in place when outlet_out == outlet_in: each element is read and
 // written by the same thread).
 template <class S>
-__device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_in, int i, int j,
+__device__ __forceinline__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_in, int i, int j,
                           typename Codec<S>::T g[NQ], bool update_outlet) {
     using T = typename Codec<S>::T;
     const Consts<T>& c = consts_of<T>(d);
     // uniform parameters, read together ahead of the lane-dependent logic
     const int nx = d.nx, ny = d.ny;
     const int kW = d.bc[0], kE = d.bc[1], kS = d.bc[2], kN = d.bc[3];
-    const unsigned pitch = (unsigned)d.pitch;
+    const long long pitch = d.pitch;
     const long long psb = d.ps * (long long)sizeof(S);
     const float is = d.inv_scale;
     const T uc = c.uc, inv1uc = c.inv1uc;
@@ -470,8 +483,8 @@ __device__ void pull_edge(const SimDesc& d, const void* fin, const void* outlet_
             dir = (fx && fy) ? ao : (fx ? ax : (fy ? ay : a));  // specular reflection
             to = o_dr + (unsigned)(a * NQ + dir) * (unsigned)sizeof(T);
         }
-        v[a] = Codec<S>::load(base + (long long)dir * psb,
-                              ((unsigned)sj * pitch + (unsigned)si) * (unsigned)sizeof(S), is);
+        v[a] = Codec<S>::load(base + (long long)dir * psb +
+                                  ((long long)sj * pitch + si) * (long long)sizeof(S), 0u, is);
         add[a] = gld(reinterpret_cast<const T*>(cbase + to));
         if (of) outflow |= 1u << a;
     }
@@ -829,7 +842,7 @@ __device__ __forceinline__ void pull_xedge(const SimDesc& d,
         kadd[k] = c.xadd[side][k];
     }
     const bool edge = WEST ? (i == 0) : (i == nx - 1);
-    const unsigned off = ((unsigned)j * (unsigned)ts.pitch + (unsigned)i) * e;
+    const unsigned off = ((unsigned)(j - ts.jb) * (unsigned)ts.pitch + (unsigned)i) * e;
     const unsigned rowb = ts.rowb;
     const char* P[NQ];
 #pragma unroll
@@ -891,7 +904,9 @@ __device__ __forceinline__ void pull_wave_edge(const SimDesc& d,
     } else if (row_inner && has_e && !has_w) {
         pull_xedge<S, false>(d, ts, i, j, g, true);
     } else if (i < nx && j < ts.ny) {
-        pull_edge<S>(d, ts.fin, d.outlet, i, j, g, true);
+        pull_edge<S>(d, reinterpret_cast<const char*>(reinterpret_cast<uintptr_t>(ts.fin) -
+                                                      (long long)ts.jb * ts.rowb),
+                     d.outlet, i, j, g, true);
     }
 }
 
@@ -924,7 +939,7 @@ __device__ __forceinline__ void pull_first(const SimDesc& d,
         const char* P[NQ];
 #pragma unroll
         for (int a = 0; a < NQ; ++a) P[a] = ts.fin + (long long)a * ts.psb;
-        pull_interior<S>(P, ((unsigned)j0 * (unsigned)ts.pitch + (unsigned)i) * (unsigned)sizeof(S),
+        pull_interior<S>(P, ((unsigned)(j0 - ts.jb) * (unsigned)ts.pitch + (unsigned)i) * (unsigned)sizeof(S),
                          ts.rowb, ts.inv_scale, g);
     } else {
         pull_wave_edge<S>(d, ts, i, j0, g);
@@ -962,7 +977,7 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
         if (j >= ny) break;  // uniform over the wave
         if (r + 1 < ROWS && j + 1 < ny) {  // uniform
             if (__all(col_inner && j + 1 <= ny - 2))
-                pull_interior<S>(P, ((unsigned)(j + 1) * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S),
+                pull_interior<S>(P, ((unsigned)(j + 1 - c.jb) * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S),
                                  rowb, is, gn);
             else
                 pull_wave_edge<S>(d, c, i, j + 1, gn);
@@ -1006,7 +1021,7 @@ __device__ __forceinline__ void step_rows(const SimDesc& d,
             } else {
                 collide<T, false>(c, g, T(0), T(0), T(0), out, o);
             }
-            const unsigned off = ((unsigned)j * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S);
+            const unsigned off = ((unsigned)(j - c.jb) * (unsigned)c.pitch + (unsigned)i) * (unsigned)sizeof(S);
 #pragma unroll
             for (int a = 0; a < NQ; ++a) Codec<S>::template store<NT>(Q[a], off, out[a], c.scale);
             if (!(o.rho > T(0)) || !__builtin_isfinite(o.ux) || !__builtin_isfinite(o.uy))
@@ -1052,13 +1067,13 @@ __device__ __forceinline__ void mem_pass(const SimDesc& d, int tx, int ty, int p
         const double d2 = disc_d2(rx, ry);
         if (d2 > band * band || (inner > 0.0 && d2 < inner * inner)) continue;
         const bool self_solid = d2 <= R2;
-        const unsigned off = node_off<S>(d, i, j);
+        const long long off = node_off<S>(d, i, j);
 #pragma unroll 1
         for (int a = 1; a < NQ; ++a) {
             const int cx = dir_cx(a), cy = dir_cy(a);
             const double nrx = (double)(i + cx) - X, nry = (double)(j + cy) - Y;
             if ((disc_d2(nrx, nry) <= R2) == self_solid) continue;
-            const double f = d.fref[a] + (double)Codec<S>::load(plane<S>(d, d.pop[p ^ 1], a), off,
+            const double f = d.fref[a] + (double)Codec<S>::load(plane<S>(d, d.pop[p ^ 1], a) + off, 0u,
                                                                  d.inv_scale);
             // fluid end (relative to the centre) and link direction towards the solid
             const double fx = self_solid ? nrx : rx, fy = self_solid ? nry : ry;
@@ -1259,7 +1274,10 @@ __device__ __forceinline__ void step_tile(const SimDesc& d, int tx, int ty, int 
     BodyDev& B = *d.body;
     // The step's scalars, then the participation box and whether this step's state is
     // final already, then the first row's populations.
-    const TileScalars<T> ts = tile_scalars<S>(d, p);
+    // the row above the tile's first: every row the tile reads or writes lies 1 to
+    // K ROWS + 1 rows below it
+    constexpr int TILE_ROWS = tile_stack(TW) * ROWS;
+    const TileScalars<T> ts = tile_scalars<S>(d, p, ty * TILE_ROWS - 1);
     const double* prev_slots = slot_base(d, sa, p ^ 1);
     // The box is read with vector-memory (buffer) loads whose values stay in vector
     // registers until the pull has been issued: a uniform load result is otherwise

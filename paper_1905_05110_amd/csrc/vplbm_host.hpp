@@ -37,26 +37,28 @@ inline long long plane_stride(int nx, int ny) {
 
 // Strides of the population arrays of one buffer (elements): between the rows of one
 // direction (SimDesc::pitch) and between directions (SimDesc::ps).  ROWS puts row j of
-// direction a at (9 j + a) pop_row_pitch: the rows a node's pull reads and the row it writes
-// then lie within a few row lengths of each other, which the memory system serves
-// faster than nine separate planes.  Kernels address populations with 32-bit byte
-// offsets from a direction's base, so ROWS needs the whole buffer, PLANES one plane,
-// below 4 GiB; returns false (with a message) when the request does not fit.
+// direction a at (9 j + a) pop_row_pitch: the rows a node's pull reads and the row it
+// writes then lie within a few row lengths of each other, which the memory system serves
+// faster than nine separate planes.  The step kernel's fast path addresses populations
+// with 32-bit lane offsets from per-tile bases at the tile's rows, so a buffer may be of
+// any size, but the rows a tile reaches (at most 18: 16 rows of a tile and one on each
+// side) must span less than 4 GiB; returns false (with a message) when the request does
+// not fit.
 inline bool pop_geometry(int nx, int ny, int storage, int request, int& pitch, long long& ps,
                          int& layout, std::string& msg) {
     const long long rp = pop_row_pitch(nx);
     const long long e = (long long)elem_size(storage);
     const long long lim = 1LL << 32;
-    const bool rows_fit = (long long)NQ * rp * ny * e < lim;
-    const bool planes_fit = plane_stride(nx, ny) * e < lim;
+    const bool rows_fit = 18 * NQ * rp * e < lim;
+    const bool planes_fit = 18 * rp * e < lim;
     if (request == LBM_LAYOUT_ROWS || (request == LBM_LAYOUT_AUTO && rows_fit)) {
-        if (!rows_fit) return msg = "grid too large for the ROWS layout (buffer of 4 GiB or more)", false;
+        if (!rows_fit) return msg = "grid too wide for the ROWS layout (18 rows span 4 GiB or more)", false;
         pitch = (int)(NQ * rp);
         ps = rp;
         layout = LBM_LAYOUT_ROWS;
         return true;
     }
-    if (!planes_fit) return msg = "grid too large: a population plane reaches 4 GiB", false;
+    if (!planes_fit) return msg = "grid too wide: 18 rows of a plane span 4 GiB or more", false;
     pitch = (int)rp;
     ps = plane_stride(nx, ny);
     layout = LBM_LAYOUT_PLANES;

@@ -107,10 +107,10 @@ __global__ void k_fill(SimDesc d, Offsets9 go, int buf) {
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     const double* g = go.g;
-    const unsigned off = node_off<S>(d, i, j);
+    const long long off = node_off<S>(d, i, j);
     for (int a = 0; a < NQ; ++a)
-        Codec<S>::template store<false>(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)g[a],
-                                        d.scale);
+        Codec<S>::template store<false>(const_cast<char*>(plane<S>(d, d.pop[buf], a)) + off, 0u,
+                                        (T)g[a], d.scale);
 }
 
 // Host FP64 populations f [9][ny][nx] <-> stored offsets.
@@ -121,11 +121,11 @@ __global__ void k_set_pop(SimDesc d, const double* __restrict__ f, int buf) {
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     const long long plane_n = (long long)d.nx * d.ny;
-    const unsigned off = node_off<S>(d, i, j);
+    const long long off = node_off<S>(d, i, j);
     for (int a = 0; a < NQ; ++a) {
         const double v = f[a * plane_n + (long long)j * d.nx + i] - d.fref[a];
-        Codec<S>::template store<false>(const_cast<char*>(plane<S>(d, d.pop[buf], a)), off, (T)v,
-                                        d.scale);
+        Codec<S>::template store<false>(const_cast<char*>(plane<S>(d, d.pop[buf], a)) + off, 0u,
+                                        (T)v, d.scale);
     }
 }
 
@@ -135,10 +135,10 @@ __global__ void k_get_pop(SimDesc d, double* __restrict__ f, int buf) {
     const int j = blockIdx.y;
     if (i >= d.nx) return;
     const long long plane_n = (long long)d.nx * d.ny;
-    const unsigned off = node_off<S>(d, i, j);
+    const long long off = node_off<S>(d, i, j);
     for (int a = 0; a < NQ; ++a)
         f[a * plane_n + (long long)j * d.nx + i] =
-            (double)Codec<S>::load(plane<S>(d, d.pop[buf], a), off, d.inv_scale) + d.fref[a];
+            (double)Codec<S>::load(plane<S>(d, d.pop[buf], a) + off, 0u, d.inv_scale) + d.fref[a];
 }
 
 // Density and penalized velocity of the current state, body at its current pose.

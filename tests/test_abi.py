@@ -61,11 +61,12 @@ def _create(lib, nx=10, ny=8, rates=(1.6, 1.5, 1.9, 1.2), eta=1e-3, **kw):
     (dict(tile_width=384), "tile_width"),
     (dict(tile_width=128), "tile_width"),
     (dict(storage="fp16", fp16_scale_log2=20), "fp16_scale"),
-    # population addresses are 32-bit byte offsets: a 24000^2 FP64 grid has planes of
-    # 4.6 GB, an 8192^2 FP64 grid a 4.8 GB buffer (too large for the ROWS layout)
-    (dict(nx=24000, ny=24000, storage="fp64"), "4 GiB"),
-    (dict(nx=8192, ny=8192, storage="fp64", layout="rows"), "4 GiB"),
-    (dict(nx=32768, ny=32768, storage="fp32"), "4 GiB"),
+    # the step's lane offsets are 32-bit from bases at the tile's rows: the 18 rows a tile
+    # reaches must span less than 4 GiB (9 directions of 3.4 M FP64 columns for the ROWS
+    # layout, one direction of 30 M FP64 or 60 M FP32 columns for either)
+    (dict(nx=3400000, ny=3, storage="fp64", layout="rows"), "4 GiB"),
+    (dict(nx=30000000, ny=3, storage="fp64"), "4 GiB"),
+    (dict(nx=60000000, ny=3, storage="fp32"), "4 GiB"),
 ])
 def test_invalid_arguments_are_rejected(lib, kw, frag):
     rc, h, msg = _create(lib, **kw)

@@ -194,6 +194,36 @@ def test_largest_rows_layout_grid_is_periodic_after_a_step(gpu, tile):
     assert np.array_equal(blocks, np.broadcast_to(ref[:, None, :, None, :], blocks.shape))
 
 
+@pytest.mark.parametrize("tile", [256, 64])
+def test_rows_layout_beyond_4_gib_is_periodic_after_a_step(gpu, tile):
+    """A population buffer beyond what 32-bit offsets from its base address: FP64 8192 x
+    8192 in the row-interleaved layout (4.87 GB per buffer), periodic on every side and
+    started from a seeded 64 x 64 pattern repeated over it.  The step addresses each tile
+    from a base at its own rows and the edge and export paths with 64-bit offsets: after
+    one step every 64 x 64 block is bitwise the step of that pattern on its own periodic
+    64 x 64 grid."""
+    nx = ny = 8192
+    n = 64
+    spec = spec_of(nx, ny, BCS["periodic"], storage="fp64", g=(2e-5, -1e-5))
+    spec.update(tile_width=tile, rows_per_tile=1, layout="rows")
+    assert gpu.load_library().lbm_pop_bytes(nx, ny, gpu.STORAGE["fp64"]) > (1 << 32)
+    pat = W.random_populations(n, n, seed=92, amp=0.05)
+    small = gpu.Sim(dict(spec, nx=n, ny=n), None)
+    small.set_populations(pat)
+    small.step(1)
+    ref = small.get_populations()
+    small.close()
+    _flush("rows layout beyond 4 GiB %dx%d fp64 tile %d" % (nx, ny, tile))
+    big = gpu.Sim(spec, None)
+    assert big.layout_name() == "rows"
+    big.set_populations(np.tile(pat, (1, ny // n, nx // n)))
+    big.step(1)
+    f = big.get_populations()
+    big.close()
+    blocks = f.reshape(9, ny // n, n, nx // n, n)
+    assert np.array_equal(blocks, np.broadcast_to(ref[:, None, :, None, :], blocks.shape))
+
+
 def test_zero_steps_and_empty_records(gpu):
     """Stepping zero steps does nothing (no record, the populations unchanged); forces
     with nothing pending returns no record."""
