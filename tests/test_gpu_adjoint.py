@@ -151,6 +151,16 @@ def test_reduced_drag_copy_finite_differences_full_length(gpu):
     adj.close()
 
 
+def test_adjoint_refuses_direction_arrays_of_4_gib(gpu):
+    """The reverse step addresses a direction's populations with 32-bit offsets from its
+    base: an FP64 8192 x 8192 grid (a direction spans 4.87 GB in the row-interleaved
+    layout, which the forward step itself runs) is refused with LBM_ERR_ARG."""
+    wl = W.adjoint_drag(storage="fp64", nx=8192, ny=8192, D=32.0)
+    with pytest.raises(gpu.LbmError) as e:
+        gpu.Adjoint(wl["spec"], wl["body"], 4, 2, (1.0, 0.0))
+    assert e.value.code == gpu.LBM_ERR_ARG and "4 GiB" in str(e.value)
+
+
 def test_repeated_backward_is_deterministic(gpu):
     spec, body = tiny("channel")
     adj = gpu.Adjoint(spec, body, 8, 4, (1.0, 0.0))
